@@ -1,0 +1,196 @@
+"""ctypes front end of the C oracle in ``sg_oracle.c``.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Every function takes and
+returns NumPy arrays; the arithmetic lives in the C file, where each routine
+cites the passage of the paper it follows.  No function here calls the HIP
+library.
+
+Parity status: every function is pinned by an independent test under
+``tests/`` (closed forms, exhaustive enumeration, textbook patterns,
+hand-derived worked examples, an independent sparse formulation).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build_oracle
+
+_lib = None
+
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+_ptr = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(build_oracle.LIB):
+        build_oracle.build()
+    lib = ctypes.CDLL(build_oracle.LIB)
+    sig = {
+        "sgo_member": (_int, [_i64, _i64]),
+        "sgo_member_paper": (_int, [_i64, _i64, _i64]),
+        "sgo_count_cells": (_i64, [_int]),
+        "sgo_lambda_grid": (None, [_int, _ptr, _ptr]),
+        "sgo_lambda": (None, [_int, _i64, _i64, _ptr, _ptr]),
+        "sgo_map_lambda": (None, [_int, _ptr]),
+        "sgo_map_bbox": (None, [_int, _int, _ptr]),
+        "sgo_write_pass": (None, [_int, ctypes.c_uint8, _ptr]),
+        "sgo_life_step_plain": (None, [_i64, _i64, _ptr, _ptr]),
+        "sgo_life_step": (None, [_int, _ptr, _ptr]),
+        "sgo_life_window": (None, [_int, _ptr, _i64, _i64, _i64, _i64, _int, _ptr]),
+        "sgo_row_checksums": (None, [_int, _ptr, _ptr, _ptr]),
+        "sgo_diffuse_step": (None, [_int, _ptr, _ptr, ctypes.c_double]),
+        "sgo_diffuse_window": (None, [_int, _ptr, _i64, _i64, _i64, _i64, _int,
+                                      ctypes.c_double, _ptr]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check_state(r: int, a: np.ndarray, dtype):
+    n = 1 << r
+    if a.dtype != dtype or a.shape != (n, n):
+        raise ValueError(f"expected {dtype} array of shape ({n}, {n}), got {a.dtype} {a.shape}")
+    return np.ascontiguousarray(a)
+
+
+# ---------------------------------------------------------------- membership
+
+def member(x: int, y: int) -> bool:
+    """Build-frame membership (x & y) == 0."""
+    return bool(_load().sgo_member(x, y))
+
+
+def member_paper(n: int, x: int, y: int) -> bool:
+    """Paper-frame membership x & (n-1-y) == 0 (Section III-D)."""
+    return bool(_load().sgo_member_paper(n, x, y))
+
+
+def count_cells(r: int) -> int:
+    """Gasket cells in the 2^r x 2^r array, by scanning every cell."""
+    return int(_load().sgo_count_cells(r))
+
+
+# ---------------------------------------------------------------- lambda
+
+def lambda_grid(rb: int):
+    """(W, H) of the launch orthotope for block level r_b (Lemma 2, Eq. 4)."""
+    W, H = ctypes.c_int64(), ctypes.c_int64()
+    _load().sgo_lambda_grid(rb, ctypes.byref(W), ctypes.byref(H))
+    return W.value, H.value
+
+
+def lambda_paper(rb: int, wx: int, wy: int):
+    """lambda(omega) in the paper frame (Eq. 4-10)."""
+    lx, ly = ctypes.c_int64(), ctypes.c_int64()
+    _load().sgo_lambda(rb, wx, wy, ctypes.byref(lx), ctypes.byref(ly))
+    return lx.value, ly.value
+
+
+def map_lambda(rb: int) -> np.ndarray:
+    """Build-frame table: row i = (bx, by) of omega with linear index i."""
+    W, H = lambda_grid(rb)
+    out = np.zeros((W * H, 2), dtype=np.uint32)
+    _load().sgo_map_lambda(rb, _p(out))
+    return out
+
+
+def map_bbox(r: int, rho: int) -> np.ndarray:
+    """Bounding-box block mask, shape (n_b, n_b), indexed [by, bx]."""
+    nb = (1 << r) // rho
+    out = np.zeros((nb, nb), dtype=np.uint8)
+    _load().sgo_map_bbox(r, rho, _p(out))
+    return out
+
+
+# ---------------------------------------------------------------- passes
+
+def write_pass(r: int, value: int) -> np.ndarray:
+    n = 1 << r
+    a = np.zeros((n, n), dtype=np.uint8)
+    _load().sgo_write_pass(r, value, _p(a))
+    return a
+
+
+def life_step_plain(a: np.ndarray) -> np.ndarray:
+    """Plain B3/S23 on an h x w grid with dead outside cells."""
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    h, w = a.shape
+    out = np.empty_like(a)
+    _load().sgo_life_step_plain(w, h, _p(a), _p(out))
+    return out
+
+
+def life_step(r: int, a: np.ndarray) -> np.ndarray:
+    a = _check_state(r, a, np.uint8)
+    out = np.empty_like(a)
+    _load().sgo_life_step(r, _p(a), _p(out))
+    return out
+
+
+def life_steps(r: int, a: np.ndarray, steps: int) -> np.ndarray:
+    a = _check_state(r, a, np.uint8)
+    cur, nxt = a.copy(), np.empty_like(a)
+    lib = _load()
+    for _ in range(steps):
+        lib.sgo_life_step(r, _p(cur), _p(nxt))
+        cur, nxt = nxt, cur
+    return cur
+
+
+def life_window(r: int, a: np.ndarray, x0: int, y0: int, w: int, h: int,
+                steps: int) -> np.ndarray:
+    """State after `steps` on the window [x0, x0+w) x [y0, y0+h)."""
+    a = _check_state(r, a, np.uint8)
+    out = np.zeros((h, w), dtype=np.uint8)
+    _load().sgo_life_window(r, _p(a), x0, y0, w, h, steps, _p(out))
+    return out
+
+
+def row_checksums(r: int, a: np.ndarray):
+    a = _check_state(r, a, np.uint8)
+    n = 1 << r
+    xr = np.zeros(n, dtype=np.uint8)
+    pop = np.zeros(n, dtype=np.uint32)
+    _load().sgo_row_checksums(r, _p(a), _p(xr), _p(pop))
+    return xr, pop
+
+
+def diffuse_step(r: int, u: np.ndarray, alpha: float = 0.2) -> np.ndarray:
+    u = _check_state(r, u, np.float64)
+    out = np.empty_like(u)
+    _load().sgo_diffuse_step(r, _p(u), _p(out), alpha)
+    return out
+
+
+def diffuse_steps(r: int, u0: np.ndarray, steps: int, alpha: float = 0.2) -> np.ndarray:
+    """FP64 diffusion from an FP32 (or FP64) initial state."""
+    cur = np.ascontiguousarray(u0, dtype=np.float64).copy()
+    _check_state(r, cur, np.float64)
+    nxt = np.empty_like(cur)
+    lib = _load()
+    for _ in range(steps):
+        lib.sgo_diffuse_step(r, _p(cur), _p(nxt), alpha)
+        cur, nxt = nxt, cur
+    return cur
+
+
+def diffuse_window(r: int, u0: np.ndarray, x0: int, y0: int, w: int, h: int,
+                   steps: int, alpha: float = 0.2) -> np.ndarray:
+    u0 = _check_state(r, u0, np.float32)
+    out = np.zeros((h, w), dtype=np.float64)
+    _load().sgo_diffuse_window(r, _p(u0), x0, y0, w, h, steps, alpha, _p(out))
+    return out

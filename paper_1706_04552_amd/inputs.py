@@ -1,0 +1,102 @@
+"""Seeded synthetic inputs, shared by the GPU path's callers and the oracle.
+
+This module holds none of the method's arithmetic.  It draws random numbers and
+places them on the cells of the gasket, the domain of every workload: cell
+(x, y) (column x, row y, 0-based) belongs to the gasket iff (x & y) == 0, and
+every other cell of the n x n embedding holds 0.
+
+Draw order: one draw per gasket cell, in row-major order, from NumPy's
+``default_rng(seed)`` (PCG64).  Rows are filled in chunks, which does not change
+the stream: consecutive calls of ``Generator.random`` continue it.
+"""
+from dataclasses import dataclass
+from typing import List
+
+import numpy as np
+
+DEFAULT_SEED = 1706
+
+
+def gasket_rows(n: int, y0: int, y1: int) -> np.ndarray:
+    """Boolean mask of the gasket cells in rows [y0, y1) of an n x n array."""
+    x = np.arange(n, dtype=np.int64)[None, :]
+    y = np.arange(y0, y1, dtype=np.int64)[:, None]
+    return (x & y) == 0
+
+
+def _row_chunk(n: int) -> int:
+    return max(1, (1 << 24) // n)
+
+
+def bernoulli_state(r: int, p: float = 0.5, seed: int = DEFAULT_SEED) -> np.ndarray:
+    """uint8 n x n state: Bernoulli(p) 0/1 on gasket cells, 0 elsewhere."""
+    n = 1 << r
+    rng = np.random.default_rng(seed)
+    a = np.zeros((n, n), dtype=np.uint8)
+    step = _row_chunk(n)
+    for y0 in range(0, n, step):
+        y1 = min(n, y0 + step)
+        m = gasket_rows(n, y0, y1)
+        k = int(m.sum())
+        a[y0:y1][m] = (rng.random(k) < p).astype(np.uint8)
+    return a
+
+
+def uniform_field(r: int, seed: int = DEFAULT_SEED) -> np.ndarray:
+    """float32 n x n field: U[0, 1) on gasket cells, 0 elsewhere."""
+    n = 1 << r
+    rng = np.random.default_rng(seed)
+    u = np.zeros((n, n), dtype=np.float32)
+    step = _row_chunk(n)
+    for y0 in range(0, n, step):
+        y1 = min(n, y0 + step)
+        m = gasket_rows(n, y0, y1)
+        k = int(m.sum())
+        u[y0:y1][m] = rng.random(k, dtype=np.float32)
+    return u
+
+
+@dataclass
+class InstanceSpec:
+    """One gasket of a batch: level r, Bernoulli p, state seed."""
+    r: int
+    p: float
+    seed: int
+
+    def state(self) -> np.ndarray:
+        return bernoulli_state(self.r, self.p, self.seed)
+
+
+def batch_specs(count: int = 512, r_lo: int = 6, r_hi: int = 13,
+                seed: int = DEFAULT_SEED) -> List[InstanceSpec]:
+    """Uneven batch: r ~ U{r_lo..r_hi}, p ~ U[0.2, 0.8], instance i seeded seed+i."""
+    rng = np.random.default_rng(seed)
+    rs = rng.integers(r_lo, r_hi + 1, size=count)
+    ps = rng.uniform(0.2, 0.8, size=count)
+    return [InstanceSpec(int(rs[i]), float(ps[i]), seed + i) for i in range(count)]
+
+
+@dataclass
+class RequestSpec:
+    """One serving request: arrival time (s), level r, CA steps, state seed."""
+    rid: int
+    arrival: float
+    r: int
+    steps: int
+    seed: int
+
+    def state(self) -> np.ndarray:
+        return bernoulli_state(self.r, 0.5, self.seed)
+
+
+def poisson_requests(qps: float, count: int, r_lo: int = 8, r_hi: int = 15,
+                     steps_lo: int = 10, steps_hi: int = 200,
+                     seed: int = DEFAULT_SEED) -> List[RequestSpec]:
+    """Poisson arrivals at rate `qps`; r ~ U{r_lo..r_hi}, steps ~ U{steps_lo..steps_hi}."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / qps, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    rs = rng.integers(r_lo, r_hi + 1, size=count)
+    st = rng.integers(steps_lo, steps_hi + 1, size=count)
+    return [RequestSpec(i, float(t[i]), int(rs[i]), int(st[i]), seed + 1000 + i)
+            for i in range(count)]
