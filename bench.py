@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark: B3/S23 life step on an r = 16 embedded Sierpinski gasket
+(n = 65,536, 3^16 = 43,046,721 cells, uint8 state), lambda(omega) block map
+against the bounding-box map, on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10]
+
+Prints ONE JSON line.  `value` is gasket cells updated per second by the
+lambda-mapped step at its best block side rho; the bounding-box map at every
+rho, the paper's write pass (lambda vs bounding box) and the roofline of the
+dominant kernel are reported beside it.  Inputs are seeded synthetic states
+(Bernoulli(0.5) on the gasket cells, seed 1706) resident in HBM before the
+timed region; the oracle's CPU time on a bounded sample is reported as
+`cpu_baseline`.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
+CA_BYTES_PER_CELL = 2          # read own state once, write it once
+WRITE_BYTES_PER_CELL = 1       # store the constant once
+RHOS = (4, 8, 16, 32)
+R = 16
+SEED = 1706
+PAPER_BEST_VS_BEST = "about 10x (best lambda, rho=16, vs best bounding box, rho=32; Titan-X Pascal GP102; write pass at n=2^16)"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_region(torch, fn, steps, warmup):
+    """Average ms per call of `fn` over `steps` calls, HIP events on the stream
+    the kernels are launched on (torch's current stream)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def traffic_from_profile(kernel_tag):
+    """HBM bytes per launch measured by rocprofv3 PMC counters, if a summary
+    for this kernel and the current kernel source is committed."""
+    path = os.path.join(HERE, "profiles", f"{kernel_tag}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    from paper_1706_04552_amd.build import source_digest
+    if rec.get("source_digest") != source_digest():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(r, a0_host):
+    """The oracle, as it stands, on a bounded sample: one generation of the
+    same r = 16 state, on the host's cores."""
+    import oracle as O
+    threads = O.threads()
+    t0 = time.perf_counter()
+    O.life_step(r, a0_host)
+    dt = time.perf_counter() - t0
+    return {"value": 3 ** r / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"1 generation of the r={r} gasket ({3 ** r} cells), dense C oracle, "
+                      f"{dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--rho", type=int, nargs="*", default=list(RHOS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              f"(the gasket path is measured on a single MI355X)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1706_04552_amd import inputs, sg
+    sg.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    n = 1 << R
+    cells = 3 ** R
+
+    log(f"generating r={R} state (n={n}, {cells} gasket cells)")
+    a0 = inputs.bernoulli_state(R, 0.5, SEED)
+    A = torch.from_numpy(a0).to(dev)
+    B = torch.zeros_like(A)
+    torch.cuda.synchronize()
+
+    results = {"lambda": {}, "bbox": {}}
+    for map_kind in ("lambda", "bbox"):
+        for rho in args.rho:
+            bufs = [A.clone(), B]
+            state = {"i": 0}
+
+            def step():
+                i = state["i"]
+                sg.sg_ca_step(map_kind, R, rho, bufs[i], bufs[1 - i])
+                state["i"] = 1 - i
+
+            ms = time_region(torch, step, args.steps, args.warmup)
+            results[map_kind][rho] = ms
+            log(f"ca {map_kind:6s} rho={rho:2d}: {ms * 1e3:9.2f} us/step  "
+                f"{cells / (ms * 1e-3) / 1e9:8.2f} Gcells/s")
+            del bufs
+            B.zero_()
+
+    best_rho = min(results["lambda"], key=lambda k: results["lambda"][k])
+    best_ms = results["lambda"][best_rho]
+    bb_best_rho = min(results["bbox"], key=lambda k: results["bbox"][k])
+
+    # the paper's experiment: write a constant on every gasket cell
+    wp = {"lambda": {}, "bbox": {}}
+    Wt = torch.zeros_like(A)
+    for map_kind in ("lambda", "bbox"):
+        for rho in args.rho:
+            wp[map_kind][rho] = time_region(
+                torch, lambda: sg.sg_write_pass(map_kind, R, rho, Wt, 1), args.steps, args.warmup)
+            log(f"write {map_kind:6s} rho={rho:2d}: {wp[map_kind][rho] * 1e3:9.2f} us")
+    del Wt
+    wl = min(wp["lambda"], key=lambda k: wp["lambda"][k])
+    wb = min(wp["bbox"], key=lambda k: wp["bbox"][k])
+
+    achieved = CA_BYTES_PER_CELL * cells / (best_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(f"k_life_rho{best_rho}_r{R}")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": traffic,
+                "kernel": f"k_life<{best_rho}, lambda>",
+                "algorithmic_bytes_per_launch": CA_BYTES_PER_CELL * cells}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle (1 generation at r=16)")
+        cpu = cpu_baseline(R, a0)
+
+    prop = torch.cuda.get_device_properties(0)
+    out = {
+        "metric": "fractal cells updated/s + % HBM peak, lambda vs bbox map, n=2^16 CA step",
+        "value": cells / (best_ms * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": best_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic: Bernoulli(0.5) uint8 on the gasket cells, seed 1706",
+        "config": {"workload": "B3/S23 life step on the r=16 embedded Sierpinski gasket "
+                               "(n=65536, 43,046,721 cells), uint8, lambda map",
+                   "r": R, "rho": best_rho, "map": "lambda", "steps_per_launch": 1},
+        "roofline": roofline,
+        "device": {"name": prop.name, "arch": getattr(prop, "gcnArchName", ""),
+                   "cus": prop.multi_processor_count,
+                   "hbm_gib": round(prop.total_memory / 2 ** 30, 1)},
+        "cpu_baseline": cpu,
+        "hbm_frac_fractal_bytes": round(achieved / PEAK_HBM_GBS, 4),
+        "lambda_vs_bbox": {
+            "us_per_step": {m: {str(k): round(v * 1e3, 3) for k, v in results[m].items()}
+                            for m in results},
+            "speedup_per_rho": {str(k): round(results["bbox"][k] / results["lambda"][k], 3)
+                                for k in results["lambda"] if k in results["bbox"]},
+            "best_vs_best": round(results["bbox"][bb_best_rho] / best_ms, 3),
+            "best_rho": {"lambda": best_rho, "bbox": bb_best_rho},
+        },
+        "write_pass": {
+            "us": {m: {str(k): round(v * 1e3, 3) for k, v in wp[m].items()} for m in wp},
+            "best_vs_best": round(wp["bbox"][wb] / wp["lambda"][wl], 3),
+            "best_rho": {"lambda": wl, "bbox": wb},
+            "lambda_cells_per_s": cells / (wp["lambda"][wl] * 1e-3),
+            "paper_context": PAPER_BEST_VS_BEST,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

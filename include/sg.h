@@ -1,0 +1,132 @@
+/*
+ * sg.h -- C ABI of libsg, the MI355X (gfx950) library for the block-space
+ * thread map lambda(omega) of "Block-space GPU Mapping for Embedded
+ * Sierpinski Gasket Fractals" (Navarro, Bustos, Vega, Hitschfeld,
+ * arXiv 1706.04552) and the data-parallel passes it feeds.
+ *
+ * Problem (Section I): a Sierpinski gasket of level r is embedded in an
+ * n x n array, n = 2^r, so that memory neighbours (x+-1, y+-1) are fractal
+ * neighbours.  A GPU pass over the gasket maps blocks of rho x rho threads
+ * (rho = 2^k) onto blocks of the array.  The bounding-box map (BB) launches
+ * all n_b x n_b blocks (n_b = n/rho) and discards the threads that fall off
+ * the gasket; lambda(omega) (Theorem 1, Eq. 4-10) launches only the
+ * 3^(r-k) blocks that hold gasket cells.
+ *
+ * Coordinates (build frame): cell (x, y) is column x, row y, 0-based,
+ * stored row-major with pitch n; it belongs to the gasket iff
+ * (x & y) == 0.  The paper's frame (origin top-left, y down, test
+ * x & (n-1-y) == 0, Section III-D) is this frame reflected by y -> n-1-y.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are DEVICE pointers (hipMalloc'd or torch tensors),
+ *    owned by the caller; the library never frees or keeps them.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call is asynchronous on that stream; the library does not
+ *    synchronise.
+ *  - Arguments are validated on the host before any HIP call, so invalid
+ *    arguments return an error with no device work queued.
+ *  - State arrays (d_a, d_in, d_out) must be 16-byte aligned; misaligned
+ *    pointers return SG_EINVAL.
+ *  - r must lie in [0, SG_MAX_R]; rho must be a power of two in
+ *    [1, SG_MAX_RHO] with rho <= n.
+ *  - State arrays are n x n and must hold 0 on every cell off the gasket
+ *    (the caller zeroes both ping-pong buffers once).  Entry points never
+ *    touch a block that holds no gasket cell; inside a block they may store
+ *    0 into cells off the gasket.  Results on inputs with non-zero cells off
+ *    the gasket are unspecified.
+ *  - Return value: SG_OK (0) or a negative sg_status.  Launch failures are
+ *    reported as SG_EHIP; faults of a running kernel surface at the caller's
+ *    next synchronisation, as for any asynchronous HIP work.
+ */
+#ifndef SG_H
+#define SG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SG_API __attribute__((visibility("default")))
+
+#define SG_MAX_R 20
+#define SG_MAX_RHO 32
+
+typedef enum sg_status {
+    SG_OK = 0,
+    SG_EINVAL = -1, /* r, rho, map kind or a size out of range; null pointer */
+    SG_EALIAS = -2, /* input and output arrays overlap */
+    SG_EHIP = -3,   /* a HIP runtime call or kernel launch failed */
+    SG_ENOMEM = -4, /* the library could not allocate what it needs */
+} sg_status;
+
+typedef enum sg_map_kind {
+    SG_MAP_LAMBDA = 0, /* lambda(omega): one block per fractal block */
+    SG_MAP_BBOX = 1    /* bounding box: every block, off-gasket threads discarded */
+} sg_map_kind;
+
+/* Human-readable text of a status code (static storage, never NULL). */
+SG_API const char *sg_strerror(int code);
+
+/* Text of the last HIP error the calling thread met inside the library, or
+ * "" if none (static per-thread storage). */
+SG_API const char *sg_last_hip_error(void);
+
+/* ABI version, bumped when a signature changes. */
+SG_API int sg_version(void);
+
+/* Host only.  Sides of the lambda launch orthotope Pi^2 for level r and
+ * block side rho (Lemma 2, Eq. 4): *W = 3^floor(r_b/2) columns (omega_x),
+ * *H = 3^ceil(r_b/2) rows (omega_y), r_b = r - log2(rho); W*H = 3^r_b.
+ * Errors: SG_EINVAL for bad r/rho or null outputs. */
+SG_API int sg_lambda_grid(int r, int rho, uint64_t *W, uint64_t *H);
+
+/* Host only.  Number of blocks the given map launches: 3^r_b for lambda,
+ * 4^r_b = n_b^2 for the bounding box (Theorem 2's parallel spaces). */
+SG_API int sg_block_count(int map, int r, int rho, uint64_t *blocks);
+
+/* lambda(omega), Theorem 1, Eq. 4-10.  Writes the block each omega maps to:
+ * d_bxy[2i] = bx, d_bxy[2i+1] = by for omega = (omega_x, omega_y) at linear
+ * index i = omega_y * W + omega_x, in the build frame
+ * (bx, by) = (lambda_x, n_b - 1 - lambda_y).
+ * d_bxy: device, 2 * 3^r_b uint32 (8-byte aligned).  Errors: SG_EINVAL. */
+SG_API int sg_map_lambda(int r, int rho, uint32_t *d_bxy, void *stream);
+
+/* Bounding-box map (Section I, Fig. 3): the identity over the n_b x n_b
+ * block grid.  d_mask[by * n_b + bx] = 1 iff block (bx, by) keeps at least
+ * one thread (holds a gasket cell), else 0.
+ * d_mask: device, n_b * n_b bytes.  Errors: SG_EINVAL. */
+SG_API int sg_map_bbox(int r, int rho, uint8_t *d_mask, void *stream);
+
+/* Write pass, the paper's experiment (Section IV): store `value` into every
+ * gasket cell of d_a; cells off the gasket keep (or get) 0.
+ * map: SG_MAP_LAMBDA or SG_MAP_BBOX (same result, different launch).
+ * d_a: device, n * n bytes, row-major.  Errors: SG_EINVAL. */
+SG_API int sg_write_pass(int map, int r, int rho, uint8_t *d_a, uint8_t value,
+                         void *stream);
+
+/* One generation of B3/S23 life on the gasket (an application of the
+ * embedded gasket, Section I): for every gasket cell, c = number of live
+ * cells among its 8 neighbours that lie in the grid and in the gasket;
+ * out = 1 iff c == 3 or (in == 1 and c == 2); cells off the gasket are 0.
+ * d_in, d_out: device, n * n bytes holding 0/1, distinct, not overlapping.
+ * Errors: SG_EINVAL, SG_EALIAS. */
+SG_API int sg_ca_step(int map, int r, int rho, const uint8_t *d_in,
+                      uint8_t *d_out, void *stream);
+
+/* One explicit diffusion step on the gasket in FP32 (a nearest-neighbour
+ * application, Section I): for every gasket cell,
+ *   out = u + alpha * sum_{nb in W, E, N, S; in grid and in gasket} (u_nb - u),
+ * summed in the order W, E, N, S; cells off the gasket are 0 and never
+ * enter a sum.
+ * d_in, d_out: device, n * n floats, distinct, not overlapping.
+ * Errors: SG_EINVAL, SG_EALIAS. */
+SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in,
+                           float *d_out, float alpha, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SG_H */

@@ -34,6 +34,7 @@ def _load():
         "sgo_member": (_int, [_i64, _i64]),
         "sgo_member_paper": (_int, [_i64, _i64, _i64]),
         "sgo_count_cells": (_i64, [_int]),
+        "sgo_threads": (_int, []),
         "sgo_lambda_grid": (None, [_int, _ptr, _ptr]),
         "sgo_lambda": (None, [_int, _i64, _i64, _ptr, _ptr]),
         "sgo_map_lambda": (None, [_int, _ptr]),
@@ -65,6 +66,11 @@ def _check_state(r: int, a: np.ndarray, dtype):
     if a.dtype != dtype or a.shape != (n, n):
         raise ValueError(f"expected {dtype} array of shape ({n}, {n}), got {a.dtype} {a.shape}")
     return np.ascontiguousarray(a)
+
+
+def threads() -> int:
+    """Threads the oracle's OpenMP row loops use."""
+    return int(_load().sgo_threads())
 
 
 # ---------------------------------------------------------------- membership

@@ -356,3 +356,11 @@ void sgo_diffuse_window(int r, const float *in, int64_t x0, int64_t y0,
     free(a);
     free(b);
 }
+
+/* Number of threads the OpenMP row loops above use. */
+#ifdef _OPENMP
+#include <omp.h>
+int sgo_threads(void) { return omp_get_max_threads(); }
+#else
+int sgo_threads(void) { return 1; }
+#endif

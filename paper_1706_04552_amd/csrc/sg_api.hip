@@ -1,0 +1,140 @@
+// C entry points of libsg: argument validation (host only, before any HIP
+// call), map/tile bookkeeping, and dispatch to the kernel launchers.
+#include <string.h>
+
+#include "../../include/sg.h"
+#include "sg_launch.h"
+
+namespace {
+
+thread_local char g_last_hip_error[256] = "";
+
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return SG_OK;
+  const char *s = hipGetErrorString(e);
+  strncpy(g_last_hip_error, s ? s : "unknown HIP error", sizeof(g_last_hip_error) - 1);
+  g_last_hip_error[sizeof(g_last_hip_error) - 1] = '\0';
+  return SG_EHIP;
+}
+
+uint64_t pow3(int e) {
+  uint64_t v = 1;
+  for (int i = 0; i < e; ++i) v *= 3;
+  return v;
+}
+
+// log2 of a power-of-two rho in [1, SG_MAX_RHO], or -1.
+int rho_log2(int rho) {
+  if (rho < 1 || rho > SG_MAX_RHO || (rho & (rho - 1)) != 0) return -1;
+  int k = 0;
+  while ((1 << k) < rho) ++k;
+  return k;
+}
+
+// Validates (r, rho) and returns r_b = r - log2(rho), or -1.
+int block_level(int r, int rho) {
+  if (r < 0 || r > SG_MAX_R) return -1;
+  const int k = rho_log2(rho);
+  if (k < 0 || k > r) return -1;
+  return r - k;
+}
+
+// State arrays are read and written with 16-byte vector accesses.
+bool misaligned(const void *p) { return ((uintptr_t)p & 15u) != 0; }
+
+bool overlaps(const void *a, const void *b, size_t bytes) {
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + bytes && pb < pa + bytes;
+}
+
+int pass_args(int map, int r, int rho, void *stream, sg::PassArgs &a) {
+  const int rb = block_level(r, rho);
+  if (rb < 0 || (map != SG_MAP_LAMBDA && map != SG_MAP_BBOX)) return SG_EINVAL;
+  a.r = r;
+  a.rho = rho;
+  a.rb = rb;
+  a.lambda = map == SG_MAP_LAMBDA;
+  a.ntiles = a.lambda ? pow3(rb) : (1ull << (2 * rb));
+  a.stream = (hipStream_t)stream;
+  return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+SG_API const char *sg_strerror(int code) {
+  switch (code) {
+    case SG_OK: return "success";
+    case SG_EINVAL: return "invalid argument (r, rho, map kind, size or null pointer)";
+    case SG_EALIAS: return "input and output arrays overlap";
+    case SG_EHIP: return "HIP runtime error";
+    case SG_ENOMEM: return "out of memory";
+    default: return "unknown status";
+  }
+}
+
+SG_API const char *sg_last_hip_error(void) { return g_last_hip_error; }
+
+SG_API int sg_version(void) { return 1; }
+
+SG_API int sg_lambda_grid(int r, int rho, uint64_t *W, uint64_t *H) {
+  const int rb = block_level(r, rho);
+  if (rb < 0 || !W || !H) return SG_EINVAL;
+  *W = pow3(rb / 2);
+  *H = pow3(rb - rb / 2);
+  return SG_OK;
+}
+
+SG_API int sg_block_count(int map, int r, int rho, uint64_t *blocks) {
+  sg::PassArgs a;
+  if (!blocks) return SG_EINVAL;
+  const int st = pass_args(map, r, rho, nullptr, a);
+  if (st != SG_OK) return st;
+  *blocks = a.ntiles;
+  return SG_OK;
+}
+
+SG_API int sg_map_lambda(int r, int rho, uint32_t *d_bxy, void *stream) {
+  const int rb = block_level(r, rho);
+  if (rb < 0 || !d_bxy || ((uintptr_t)d_bxy & 7u)) return SG_EINVAL;
+  return hip_status(sg::launch_map_lambda(rb, (uint32_t)pow3(rb), d_bxy, (hipStream_t)stream));
+}
+
+SG_API int sg_map_bbox(int r, int rho, uint8_t *d_mask, void *stream) {
+  const int rb = block_level(r, rho);
+  if (rb < 0 || !d_mask) return SG_EINVAL;
+  return hip_status(sg::launch_map_bbox(rb, 1ull << (2 * rb), d_mask, (hipStream_t)stream));
+}
+
+SG_API int sg_write_pass(int map, int r, int rho, uint8_t *d_a, uint8_t value, void *stream) {
+  sg::PassArgs a;
+  const int st = pass_args(map, r, rho, stream, a);
+  if (st != SG_OK) return st;
+  if (!d_a || misaligned(d_a)) return SG_EINVAL;
+  return hip_status(sg::launch_write(a, d_a, value));
+}
+
+SG_API int sg_ca_step(int map, int r, int rho, const uint8_t *d_in, uint8_t *d_out,
+                      void *stream) {
+  sg::PassArgs a;
+  const int st = pass_args(map, r, rho, stream, a);
+  if (st != SG_OK) return st;
+  if (!d_in || !d_out || misaligned(d_in) || misaligned(d_out)) return SG_EINVAL;
+  const size_t bytes = ((size_t)1 << r) * ((size_t)1 << r);
+  if (overlaps(d_in, d_out, bytes)) return SG_EALIAS;
+  return hip_status(sg::launch_life(a, d_in, d_out));
+}
+
+SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in, float *d_out,
+                           float alpha, void *stream) {
+  sg::PassArgs a;
+  const int st = pass_args(map, r, rho, stream, a);
+  if (st != SG_OK) return st;
+  if (!d_in || !d_out || misaligned(d_in) || misaligned(d_out)) return SG_EINVAL;
+  const size_t bytes = ((size_t)1 << r) * ((size_t)1 << r) * sizeof(float);
+  if (overlaps(d_in, d_out, bytes)) return SG_EALIAS;
+  return hip_status(sg::launch_diffuse(a, d_in, d_out, alpha));
+}
+
+}  // extern "C"

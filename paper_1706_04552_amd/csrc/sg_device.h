@@ -1,0 +1,132 @@
+// Device-side building blocks shared by the gasket kernels (gfx950, wave64).
+//
+// Tile model.  A "tile" is one rho x rho block of the n x n embedding.  One
+// lane owns one row of one tile (rho <= 32 contiguous cells), so a wave holds
+// 64/rho whole tiles with the tile's rows in consecutive lanes.  Row-major
+// loads of a tile row are contiguous (coalesced into rho bytes, or 4*rho for
+// FP32, per lane); the rows above and below come from the neighbouring lanes
+// through DPP wave shifts, and only the tile's first and last rows fetch a
+// halo row from memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg {
+
+constexpr int kWG = 256;  // threads per workgroup: 4 wave64
+
+// lambda(omega) decoded per block (Theorem 1, Eq. 4-10).
+//
+// omega is the linear index omega_y * W + omega_x with W = 3^floor(rb/2), so
+// the base-3 digits of omega are omega_x's digits (low floor(rb/2) digits)
+// followed by omega_y's.  Digit j of omega_x is beta at scale level
+// mu = 2j + 2 and digit j of omega_y is beta at mu = 2j + 1 (Eq. 4), each
+// contributing 2^(mu-1) (Eq. 6-7).  beta = 2 sets the x bit and beta >= 1 the
+// y bit (Eq. 5).  The result is reflected into the build frame:
+// by = n_b - 1 - lambda_y, i.e. the complement of lambda_y's r_b bits.
+__device__ __forceinline__ void lambda_decode(uint32_t w, int rb, uint32_t &bx,
+                                              uint32_t &by) {
+  uint32_t lx = 0, ly = 0;
+  const int hx = rb >> 1;
+  for (int j = 0; j < rb; ++j) {
+    const uint32_t q = w / 3u;
+    const uint32_t d = w - 3u * q;
+    w = q;
+    const int bit = (j < hx) ? (2 * j + 1) : (2 * (j - hx));
+    lx |= (uint32_t)(d == 2u) << bit;
+    ly |= (uint32_t)(d != 0u) << bit;
+  }
+  bx = lx;
+  by = ly ^ ((1u << rb) - 1u);
+}
+
+// Lane i receives lane i-1's value (DPP wave_shr:1); lane 0 receives 0.
+__device__ __forceinline__ uint32_t from_prev_lane(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);
+}
+// Lane i receives lane i+1's value (DPP wave_shl:1); lane 63 receives 0.
+__device__ __forceinline__ uint32_t from_next_lane(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ float from_prev_lane(float v) {
+  return __uint_as_float(from_prev_lane(__float_as_uint(v)));
+}
+__device__ __forceinline__ float from_next_lane(float v) {
+  return __uint_as_float(from_next_lane(__float_as_uint(v)));
+}
+
+// ---------------------------------------------------------------- u8 rows
+//
+// A row of RHO bytes lives in NW 32-bit words, little-endian: byte i of the
+// row is byte (i & 3) of word i >> 2.  For RHO < 4 only the low RHO bytes of
+// word 0 are meaningful and the loads zero-extend.
+
+template <int RHO>
+struct U8Row {
+  static constexpr int NW = RHO >= 4 ? RHO / 4 : 1;
+  uint32_t w[NW];
+};
+
+template <int RHO>
+__device__ __forceinline__ void load_row(U8Row<RHO> &row, const uint8_t *p) {
+  if constexpr (RHO == 1) {
+    row.w[0] = p[0];
+  } else if constexpr (RHO == 2) {
+    row.w[0] = *reinterpret_cast<const uint16_t *>(p);
+  } else if constexpr (RHO == 4) {
+    row.w[0] = *reinterpret_cast<const uint32_t *>(p);
+  } else if constexpr (RHO == 8) {
+    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    row.w[0] = v.x;
+    row.w[1] = v.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < RHO / 16; ++k) {
+      const uint4 v = reinterpret_cast<const uint4 *>(p)[k];
+      row.w[4 * k + 0] = v.x;
+      row.w[4 * k + 1] = v.y;
+      row.w[4 * k + 2] = v.z;
+      row.w[4 * k + 3] = v.w;
+    }
+  }
+}
+
+template <int RHO>
+__device__ __forceinline__ void store_row(uint8_t *p, const U8Row<RHO> &row) {
+  if constexpr (RHO == 1) {
+    p[0] = (uint8_t)row.w[0];
+  } else if constexpr (RHO == 2) {
+    *reinterpret_cast<uint16_t *>(p) = (uint16_t)row.w[0];
+  } else if constexpr (RHO == 4) {
+    *reinterpret_cast<uint32_t *>(p) = row.w[0];
+  } else if constexpr (RHO == 8) {
+    *reinterpret_cast<uint2 *>(p) = make_uint2(row.w[0], row.w[1]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < RHO / 16; ++k)
+      reinterpret_cast<uint4 *>(p)[k] =
+          make_uint4(row.w[4 * k], row.w[4 * k + 1], row.w[4 * k + 2], row.w[4 * k + 3]);
+  }
+}
+
+template <int RHO>
+__device__ __forceinline__ void zero_row(U8Row<RHO> &row) {
+#pragma unroll
+  for (int k = 0; k < U8Row<RHO>::NW; ++k) row.w[k] = 0u;
+}
+
+// Bounding sub-box test for a whole tile row (Section III-D): byte i of word
+// set to 1 iff (i & ty) == 0, i.e. cell (X0 + i, Y0 + ty) of a fractal tile
+// lies on the gasket (X0 & Y0 == 0 and both are multiples of rho).
+template <int RHO>
+__device__ __forceinline__ uint32_t row_mask_word(int k, uint32_t ty) {
+  uint32_t m = 0x01010101u;
+  if (ty & 1u) m &= 0x00010001u;
+  if (ty & 2u) m &= 0x00000101u;
+  if (((uint32_t)k << 2) & ty) m = 0u;
+  if constexpr (RHO < 4) m &= (1u << (8 * RHO)) - 1u;
+  return m;
+}
+
+}  // namespace sg

@@ -1,0 +1,383 @@
+// HIP kernels for gfx950: the lambda and bounding-box block maps, and the
+// passes they feed (write, B3/S23 life, FP32 diffusion).
+//
+// Every pass shares one tile body between the two maps; only the block ->
+// tile assignment differs:
+//   lambda: workgroup slot s of workgroup g takes omega = g * TPG + s and
+//           decodes it with lambda (Eq. 4-10): 3^r_b tiles, all fractal.
+//   bbox:   the same slot takes block t = g * TPG + s of the n_b x n_b grid
+//           under the identity (bx, by) = (t mod n_b, t div n_b) and discards
+//           the tile's lanes unless bx & by == 0: 4^r_b tiles.
+// Inside a fractal tile the lanes use bounding sub-boxes (Section III-D):
+// every lane keeps its row and masks cells with (tx & ty) != 0.
+#include "sg_device.h"
+#include "sg_launch.h"
+
+namespace sg {
+
+namespace {
+
+// Tile assignment for slot `slot` of this workgroup.  Returns false when the
+// slot holds no fractal tile (ragged tail, or a discarded bbox block).
+template <bool LAMBDA>
+__device__ __forceinline__ bool tile_of(uint64_t tile_base, uint64_t ntiles,
+                                        int tpg, int slot, int rb, uint32_t &bx,
+                                        uint32_t &by) {
+  const uint64_t t = tile_base + (uint64_t)blockIdx.x * (uint64_t)tpg + (uint64_t)slot;
+  if (t >= ntiles) return false;
+  if constexpr (LAMBDA) {
+    lambda_decode((uint32_t)t, rb, bx, by);
+    return true;
+  } else {
+    by = (uint32_t)(t >> rb);
+    bx = (uint32_t)(t & ((1ull << rb) - 1ull));
+    return (bx & by) == 0u;
+  }
+}
+
+// ------------------------------------------------------------------ maps
+
+__global__ __launch_bounds__(kWG) void k_map_lambda(uint2 *__restrict__ out,
+                                                    int rb, uint32_t count) {
+  const uint32_t i = blockIdx.x * kWG + threadIdx.x;
+  if (i >= count) return;
+  uint32_t bx, by;
+  lambda_decode(i, rb, bx, by);
+  out[i] = make_uint2(bx, by);
+}
+
+__global__ __launch_bounds__(kWG) void k_map_bbox(uint8_t *__restrict__ mask,
+                                                  int rb, uint64_t base,
+                                                  uint64_t count) {
+  const uint64_t t = base + (uint64_t)blockIdx.x * kWG + threadIdx.x;
+  if (t >= count) return;
+  const uint32_t by = (uint32_t)(t >> rb);
+  const uint32_t bx = (uint32_t)(t & ((1ull << rb) - 1ull));
+  mask[t] = (uint8_t)((bx & by) == 0u);
+}
+
+// ------------------------------------------------------------------ write pass
+
+template <int RHO, bool LAMBDA>
+__global__ __launch_bounds__(kWG) void k_write(uint8_t *__restrict__ a, int r,
+                                               int rb, uint64_t tile_base,
+                                               uint64_t ntiles, uint32_t value) {
+  constexpr int TPG = kWG / RHO;
+  const int slot = threadIdx.x / RHO;
+  const uint32_t ty = threadIdx.x % RHO;
+  uint32_t bx, by;
+  if (!tile_of<LAMBDA>(tile_base, ntiles, TPG, slot, rb, bx, by)) return;
+  const size_t n = (size_t)1 << r;
+  const size_t y = (size_t)by * RHO + ty;
+  const size_t x0 = (size_t)bx * RHO;
+  U8Row<RHO> row;
+#pragma unroll
+  for (int k = 0; k < U8Row<RHO>::NW; ++k) row.w[k] = row_mask_word<RHO>(k, ty) * value;
+  store_row<RHO>(a + y * n + x0, row);
+}
+
+// ------------------------------------------------------------------ life
+
+// Byte i <- byte i-1 of the row, byte 0 <- `in` (a 0..255 value).
+template <int RHO>
+__device__ __forceinline__ void shift_in_left(U8Row<RHO> &o, const U8Row<RHO> &v,
+                                              uint32_t in) {
+  constexpr int NW = U8Row<RHO>::NW;
+  if constexpr (RHO < 4) {
+    o.w[0] = ((v.w[0] << 8) | in) & ((1u << (8 * RHO)) - 1u);
+  } else {
+    o.w[0] = (v.w[0] << 8) | in;
+#pragma unroll
+    for (int k = 1; k < NW; ++k) o.w[k] = (v.w[k] << 8) | (v.w[k - 1] >> 24);
+  }
+}
+
+// Byte i <- byte i+1 of the row, byte RHO-1 <- `in`.
+template <int RHO>
+__device__ __forceinline__ void shift_in_right(U8Row<RHO> &o, const U8Row<RHO> &v,
+                                               uint32_t in) {
+  constexpr int NW = U8Row<RHO>::NW;
+  if constexpr (RHO < 4) {
+    o.w[0] = (v.w[0] >> 8) | (in << (8 * (RHO - 1)));
+  } else {
+#pragma unroll
+    for (int k = 0; k < NW - 1; ++k) o.w[k] = (v.w[k] >> 8) | (v.w[k + 1] << 24);
+    o.w[NW - 1] = (v.w[NW - 1] >> 8) | (in << 24);
+  }
+}
+
+__device__ __forceinline__ bool on_gasket(size_t x, size_t y) { return (x & y) == 0; }
+
+template <int RHO, bool LAMBDA>
+__global__ __launch_bounds__(kWG) void k_life(const uint8_t *__restrict__ in,
+                                              uint8_t *__restrict__ out, int r,
+                                              int rb, uint64_t tile_base,
+                                              uint64_t ntiles) {
+  constexpr int TPG = kWG / RHO;
+  constexpr int NW = U8Row<RHO>::NW;
+  const int slot = threadIdx.x / RHO;
+  const uint32_t ty = threadIdx.x % RHO;
+  uint32_t bx, by;
+  if (!tile_of<LAMBDA>(tile_base, ntiles, TPG, slot, rb, bx, by)) return;
+
+  const size_t n = (size_t)1 << r;
+  const size_t X0 = (size_t)bx * RHO, Y0 = (size_t)by * RHO;
+  const size_t y = Y0 + ty;
+  const bool has_l = X0 > 0, has_r = X0 + RHO < n;
+  const size_t xl = X0 - 1, xr = X0 + RHO;
+
+  // own row and its left/right neighbour cells (neighbouring tiles)
+  U8Row<RHO> C;
+  load_row<RHO>(C, in + y * n + X0);
+  uint32_t cl = (has_l && on_gasket(xl, y)) ? in[y * n + xl] : 0u;
+  uint32_t cr = (has_r && on_gasket(xr, y)) ? in[y * n + xr] : 0u;
+
+  // rows above / below: neighbouring lanes, or a halo row for the tile edges
+  U8Row<RHO> U, D;
+  uint32_t ul = from_prev_lane(cl), ur = from_prev_lane(cr);
+  uint32_t dl = from_next_lane(cl), dr = from_next_lane(cr);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    U.w[k] = from_prev_lane(C.w[k]);
+    D.w[k] = from_next_lane(C.w[k]);
+  }
+  if (ty == 0) {
+    zero_row<RHO>(U);
+    ul = ur = 0u;
+    if (Y0 > 0) {
+      const size_t yu = Y0 - 1;
+      if (on_gasket(X0, yu)) load_row<RHO>(U, in + yu * n + X0);
+      if (has_l && on_gasket(xl, yu)) ul = in[yu * n + xl];
+      if (has_r && on_gasket(xr, yu)) ur = in[yu * n + xr];
+    }
+  }
+  if (ty == RHO - 1) {
+    zero_row<RHO>(D);
+    dl = dr = 0u;
+    if (Y0 + RHO < n) {
+      const size_t yd = Y0 + RHO;
+      if (on_gasket(X0, yd)) load_row<RHO>(D, in + yd * n + X0);
+      if (has_l && on_gasket(xl, yd)) dl = in[yd * n + xl];
+      if (has_r && on_gasket(xr, yd)) dr = in[yd * n + xr];
+    }
+  }
+
+  // column sums of the 3 rows, then the 3-wide horizontal sum (bytes <= 9)
+  U8Row<RHO> V, L, R, O;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) V.w[k] = U.w[k] + C.w[k] + D.w[k];
+  shift_in_left<RHO>(L, V, ul + cl + dl);
+  shift_in_right<RHO>(R, V, ur + cr + dr);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const uint32_t cnt = L.w[k] + V.w[k] + R.w[k] - C.w[k];  // live neighbours
+    // B3/S23: alive iff (cnt | self) == 3, tested per byte on 4-bit values
+    const uint32_t x = (cnt | C.w[k]) ^ 0x03030303u;
+    uint32_t z = x | (x >> 1);
+    z |= z >> 2;
+    O.w[k] = ~z & row_mask_word<RHO>(k, ty);
+  }
+  store_row<RHO>(out + y * n + X0, O);
+}
+
+// ------------------------------------------------------------------ diffusion
+
+template <int RHO>
+struct F32Row {
+  float v[RHO];
+};
+
+template <int RHO>
+__device__ __forceinline__ void load_frow(F32Row<RHO> &row, const float *p) {
+  if constexpr (RHO == 1) {
+    row.v[0] = p[0];
+  } else if constexpr (RHO == 2) {
+    const float2 t = *reinterpret_cast<const float2 *>(p);
+    row.v[0] = t.x;
+    row.v[1] = t.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < RHO / 4; ++k) {
+      const float4 t = reinterpret_cast<const float4 *>(p)[k];
+      row.v[4 * k + 0] = t.x;
+      row.v[4 * k + 1] = t.y;
+      row.v[4 * k + 2] = t.z;
+      row.v[4 * k + 3] = t.w;
+    }
+  }
+}
+
+template <int RHO>
+__device__ __forceinline__ void store_frow(float *p, const F32Row<RHO> &row) {
+  if constexpr (RHO == 1) {
+    p[0] = row.v[0];
+  } else if constexpr (RHO == 2) {
+    *reinterpret_cast<float2 *>(p) = make_float2(row.v[0], row.v[1]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < RHO / 4; ++k)
+      reinterpret_cast<float4 *>(p)[k] =
+          make_float4(row.v[4 * k], row.v[4 * k + 1], row.v[4 * k + 2], row.v[4 * k + 3]);
+  }
+}
+
+template <int RHO, bool LAMBDA>
+__global__ __launch_bounds__(kWG) void k_diffuse(const float *__restrict__ in,
+                                                 float *__restrict__ out, int r,
+                                                 int rb, uint64_t tile_base,
+                                                 uint64_t ntiles, float alpha) {
+  constexpr int TPG = kWG / RHO;
+  const int slot = threadIdx.x / RHO;
+  const uint32_t ty = threadIdx.x % RHO;
+  uint32_t bx, by;
+  if (!tile_of<LAMBDA>(tile_base, ntiles, TPG, slot, rb, bx, by)) return;
+
+  const size_t n = (size_t)1 << r;
+  const size_t X0 = (size_t)bx * RHO, Y0 = (size_t)by * RHO;
+  const size_t y = Y0 + ty;
+  const bool has_l = X0 > 0, has_r = X0 + RHO < n;
+  const bool has_u = y > 0, has_d = y + 1 < n;
+  const size_t xl = X0 - 1, xr = X0 + RHO;
+
+  F32Row<RHO> C, U, D, O;
+  load_frow<RHO>(C, in + y * n + X0);
+  const bool ml = has_l && on_gasket(xl, y), mr = has_r && on_gasket(xr, y);
+  const float cl = ml ? in[y * n + xl] : 0.0f;
+  const float cr = mr ? in[y * n + xr] : 0.0f;
+#pragma unroll
+  for (int i = 0; i < RHO; ++i) {
+    U.v[i] = from_prev_lane(C.v[i]);
+    D.v[i] = from_next_lane(C.v[i]);
+  }
+  if (ty == 0) {
+#pragma unroll
+    for (int i = 0; i < RHO; ++i) U.v[i] = 0.0f;
+    if (Y0 > 0 && on_gasket(X0, Y0 - 1)) load_frow<RHO>(U, in + (Y0 - 1) * n + X0);
+  }
+  if (ty == RHO - 1) {
+#pragma unroll
+    for (int i = 0; i < RHO; ++i) D.v[i] = 0.0f;
+    if (Y0 + RHO < n && on_gasket(X0, Y0 + RHO)) load_frow<RHO>(D, in + (Y0 + RHO) * n + X0);
+  }
+
+#pragma unroll
+  for (int i = 0; i < RHO; ++i) {
+    const size_t x = X0 + i;
+    const float u = C.v[i];
+    const bool mw = (i == 0) ? ml : on_gasket(x - 1, y);
+    const bool me = (i == RHO - 1) ? mr : on_gasket(x + 1, y);
+    const bool mn = has_u && on_gasket(x, y - 1);
+    const bool ms = has_d && on_gasket(x, y + 1);
+    const float w = (i == 0) ? cl : C.v[i - 1];
+    const float e = (i == RHO - 1) ? cr : C.v[i + 1];
+    float s = 0.0f;
+    s += mw ? (w - u) : 0.0f;
+    s += me ? (e - u) : 0.0f;
+    s += mn ? (U.v[i] - u) : 0.0f;
+    s += ms ? (D.v[i] - u) : 0.0f;
+    O.v[i] = on_gasket(x, y) ? u + alpha * s : 0.0f;
+  }
+  store_frow<RHO>(out + y * n + X0, O);
+}
+
+// ------------------------------------------------------------------ launchers
+
+// HIP bounds gridDim.x * blockDim.x below 2^32; launches are split into
+// chunks of at most this many workgroups.
+constexpr uint64_t kMaxGroupsPerLaunch = 1ull << 23;
+
+template <typename F>
+hipError_t launch_tiles(uint64_t ntiles, int tpg, hipStream_t s, F &&launch_one) {
+  const uint64_t groups = (ntiles + tpg - 1) / tpg;
+  for (uint64_t g0 = 0; g0 < groups; g0 += kMaxGroupsPerLaunch) {
+    const uint64_t g = groups - g0 < kMaxGroupsPerLaunch ? groups - g0 : kMaxGroupsPerLaunch;
+    launch_one(dim3((unsigned)g), g0 * (uint64_t)tpg, s);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int RHO>
+hipError_t write_rho(const PassArgs &a, uint8_t *d, uint32_t value) {
+  return launch_tiles(a.ntiles, kWG / RHO, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
+    if (a.lambda)
+      hipLaunchKernelGGL((k_write<RHO, true>), grid, dim3(kWG), 0, s, d, a.r, a.rb, base, a.ntiles, value);
+    else
+      hipLaunchKernelGGL((k_write<RHO, false>), grid, dim3(kWG), 0, s, d, a.r, a.rb, base, a.ntiles, value);
+  });
+}
+
+template <int RHO>
+hipError_t life_rho(const PassArgs &a, const uint8_t *in, uint8_t *out) {
+  return launch_tiles(a.ntiles, kWG / RHO, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
+    if (a.lambda)
+      hipLaunchKernelGGL((k_life<RHO, true>), grid, dim3(kWG), 0, s, in, out, a.r, a.rb, base, a.ntiles);
+    else
+      hipLaunchKernelGGL((k_life<RHO, false>), grid, dim3(kWG), 0, s, in, out, a.r, a.rb, base, a.ntiles);
+  });
+}
+
+template <int RHO>
+hipError_t diffuse_rho(const PassArgs &a, const float *in, float *out, float alpha) {
+  return launch_tiles(a.ntiles, kWG / RHO, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
+    if (a.lambda)
+      hipLaunchKernelGGL((k_diffuse<RHO, true>), grid, dim3(kWG), 0, s, in, out, a.r, a.rb, base, a.ntiles, alpha);
+    else
+      hipLaunchKernelGGL((k_diffuse<RHO, false>), grid, dim3(kWG), 0, s, in, out, a.r, a.rb, base, a.ntiles, alpha);
+  });
+}
+
+}  // namespace
+
+hipError_t launch_map_lambda(int rb, uint32_t count, uint32_t *d_bxy, hipStream_t s) {
+  const uint32_t groups = (count + kWG - 1) / kWG;
+  if (groups == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_map_lambda, dim3(groups), dim3(kWG), 0, s,
+                     reinterpret_cast<uint2 *>(d_bxy), rb, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_bbox(int rb, uint64_t count, uint8_t *d_mask, hipStream_t s) {
+  return launch_tiles(count, kWG, s, [&](dim3 grid, uint64_t base, hipStream_t st) {
+    hipLaunchKernelGGL(k_map_bbox, grid, dim3(kWG), 0, st, d_mask, rb, base, count);
+  });
+}
+
+hipError_t launch_write(const PassArgs &a, uint8_t *d, uint8_t value) {
+  switch (a.rho) {
+    case 1: return write_rho<1>(a, d, value);
+    case 2: return write_rho<2>(a, d, value);
+    case 4: return write_rho<4>(a, d, value);
+    case 8: return write_rho<8>(a, d, value);
+    case 16: return write_rho<16>(a, d, value);
+    case 32: return write_rho<32>(a, d, value);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_life(const PassArgs &a, const uint8_t *in, uint8_t *out) {
+  switch (a.rho) {
+    case 1: return life_rho<1>(a, in, out);
+    case 2: return life_rho<2>(a, in, out);
+    case 4: return life_rho<4>(a, in, out);
+    case 8: return life_rho<8>(a, in, out);
+    case 16: return life_rho<16>(a, in, out);
+    case 32: return life_rho<32>(a, in, out);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_diffuse(const PassArgs &a, const float *in, float *out, float alpha) {
+  switch (a.rho) {
+    case 1: return diffuse_rho<1>(a, in, out, alpha);
+    case 2: return diffuse_rho<2>(a, in, out, alpha);
+    case 4: return diffuse_rho<4>(a, in, out, alpha);
+    case 8: return diffuse_rho<8>(a, in, out, alpha);
+    case 16: return diffuse_rho<16>(a, in, out, alpha);
+    case 32: return diffuse_rho<32>(a, in, out, alpha);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace sg

@@ -1,0 +1,26 @@
+// Host-side launchers of the gasket kernels (internal to libsg).  Arguments
+// reach these functions already validated by the C entry points.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sg {
+
+// One pass over the tiles of a map.
+struct PassArgs {
+  int r;            // level: n = 2^r
+  int rho;          // tile side, a power of two in [1, 32]
+  int rb;           // block level r - log2(rho)
+  bool lambda;      // lambda map (3^rb tiles) or bounding box (4^rb tiles)
+  uint64_t ntiles;  // number of tiles the map launches
+  hipStream_t stream;
+};
+
+hipError_t launch_map_lambda(int rb, uint32_t count, uint32_t *d_bxy, hipStream_t s);
+hipError_t launch_map_bbox(int rb, uint64_t count, uint8_t *d_mask, hipStream_t s);
+hipError_t launch_write(const PassArgs &a, uint8_t *d, uint8_t value);
+hipError_t launch_life(const PassArgs &a, const uint8_t *in, uint8_t *out);
+hipError_t launch_diffuse(const PassArgs &a, const float *in, float *out, float alpha);
+
+}  // namespace sg

@@ -1,0 +1,171 @@
+"""Thin ctypes binding of libsg (``include/sg.h``) over torch device tensors.
+
+Each function has the name and argument order of its C entry point; it only
+checks and marshals arguments (tensor device, dtype, shape, contiguity) and
+passes raw device pointers plus the current HIP stream.  All computation runs
+in the HIP kernels of ``libsg.so``; there is no CPU fallback: if the library
+is missing or the device is not a GPU, the call raises.
+"""
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch  # must load before libsg so both share torch's HIP runtime
+
+from . import build as _build
+
+SG_OK, SG_EINVAL, SG_EALIAS, SG_EHIP, SG_ENOMEM = 0, -1, -2, -3, -4
+SG_MAP_LAMBDA, SG_MAP_BBOX = 0, 1
+SG_MAX_R, SG_MAX_RHO = 20, 32
+MAPS = {"lambda": SG_MAP_LAMBDA, "bbox": SG_MAP_BBOX}
+
+# Every symbol declared in include/sg.h, with its ctypes signature.
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_SIGNATURES = {
+    "sg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "sg_last_hip_error": (ctypes.c_char_p, []),
+    "sg_version": (ctypes.c_int, []),
+    "sg_lambda_grid": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _u64p, _u64p]),
+    "sg_block_count": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _u64p]),
+    "sg_map_lambda": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_map_bbox": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_write_pass": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_uint8, ctypes.c_void_p]),
+    "sg_ca_step": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_diffuse_step": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
+}
+
+
+class SgError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = _lib
+        msg = lib.sg_strerror(code).decode() if lib is not None else str(code)
+        if code == SG_EHIP and lib is not None:
+            msg += f" ({lib.sg_last_hip_error().decode()})"
+        super().__init__(f"{where}: {msg} [status {code}]")
+        self.code = code
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def load() -> ctypes.CDLL:
+    """Load libsg.so (building it first only if it has never been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB):
+        _build.build()
+    lib = ctypes.CDLL(_build.LIB)
+    for name, (res, args) in _SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(code: int, where: str):
+    if code != SG_OK:
+        raise SgError(code, where)
+
+
+def _map(m) -> int:
+    if isinstance(m, str):
+        return MAPS[m]
+    return int(m)
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, numel: Optional[int], name: str) -> ctypes.c_void_p:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (got {t.device}); libsg has no CPU path")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must hold {numel} elements, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _n2(r: int) -> int:
+    if not 0 <= r <= SG_MAX_R:
+        raise SgError(SG_EINVAL, f"r={r}")
+    return (1 << r) * (1 << r)
+
+
+# ---------------------------------------------------------------- host helpers
+
+def sg_lambda_grid(r: int, rho: int) -> Tuple[int, int]:
+    W, H = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load().sg_lambda_grid(r, rho, ctypes.byref(W), ctypes.byref(H)), "sg_lambda_grid")
+    return W.value, H.value
+
+
+def sg_block_count(map_kind, r: int, rho: int) -> int:
+    b = ctypes.c_uint64()
+    _check(load().sg_block_count(_map(map_kind), r, rho, ctypes.byref(b)), "sg_block_count")
+    return b.value
+
+
+def sg_version() -> int:
+    return load().sg_version()
+
+
+# ---------------------------------------------------------------- device calls
+
+def sg_map_lambda(r: int, rho: int, d_bxy: torch.Tensor, stream=None) -> torch.Tensor:
+    """Fill d_bxy (int32/uint32 tensor of 2*3^r_b elements) with (bx, by) pairs."""
+    W, H = sg_lambda_grid(r, rho)
+    if d_bxy.dtype not in (torch.int32, torch.uint32):
+        raise TypeError("d_bxy must be int32 or uint32")
+    p = _dev(d_bxy, d_bxy.dtype, 2 * W * H, "d_bxy")
+    _check(load().sg_map_lambda(r, rho, p, _stream(stream)), "sg_map_lambda")
+    return d_bxy
+
+
+def sg_map_bbox(r: int, rho: int, d_mask: torch.Tensor, stream=None) -> torch.Tensor:
+    nb = (1 << r) // rho if rho > 0 else 0
+    p = _dev(d_mask, torch.uint8, nb * nb, "d_mask")
+    _check(load().sg_map_bbox(r, rho, p, _stream(stream)), "sg_map_bbox")
+    return d_mask
+
+
+def sg_write_pass(map_kind, r: int, rho: int, d_a: torch.Tensor, value: int = 1,
+                  stream=None) -> torch.Tensor:
+    p = _dev(d_a, torch.uint8, _n2(r), "d_a")
+    _check(load().sg_write_pass(_map(map_kind), r, rho, p, value, _stream(stream)), "sg_write_pass")
+    return d_a
+
+
+def sg_ca_step(map_kind, r: int, rho: int, d_in: torch.Tensor, d_out: torch.Tensor,
+               stream=None) -> torch.Tensor:
+    n2 = _n2(r)
+    pi = _dev(d_in, torch.uint8, n2, "d_in")
+    po = _dev(d_out, torch.uint8, n2, "d_out")
+    _check(load().sg_ca_step(_map(map_kind), r, rho, pi, po, _stream(stream)), "sg_ca_step")
+    return d_out
+
+
+def sg_diffuse_step(map_kind, r: int, rho: int, d_in: torch.Tensor, d_out: torch.Tensor,
+                    alpha: float = 0.2, stream=None) -> torch.Tensor:
+    n2 = _n2(r)
+    pi = _dev(d_in, torch.float32, n2, "d_in")
+    po = _dev(d_out, torch.float32, n2, "d_out")
+    _check(load().sg_diffuse_step(_map(map_kind), r, rho, pi, po, alpha, _stream(stream)),
+           "sg_diffuse_step")
+    return d_out

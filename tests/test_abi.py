@@ -1,0 +1,130 @@
+"""CPU tests of the C ABI: the library loads, exports every symbol that
+``include/sg.h`` declares, and rejects invalid arguments on the host before any
+HIP call (so no GPU is needed).  Host-only helpers are checked against the
+closed forms of Lemma 1-2 and Theorem 2."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sg.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"SG_API\s+[\w\s\*]+?\b(sg_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1706_04552_amd import sg
+    return sg.load()
+
+
+def test_header_declares_the_entry_points():
+    syms = declared_symbols()
+    for name in ["sg_map_lambda", "sg_map_bbox", "sg_write_pass", "sg_ca_step",
+                 "sg_diffuse_step", "sg_strerror"]:
+        assert name in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_1706_04552_amd import sg
+    out = subprocess.run(["nm", "-D", "--defined-only", sg.library_path()],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT\s+(sg_\w+)", out))
+    for name in declared_symbols():
+        assert name in exported, name
+        getattr(lib, name)
+    # nothing else leaks from the library's C namespace
+    assert exported == set(declared_symbols())
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1706_04552_amd import sg
+    assert set(sg._SIGNATURES) == set(declared_symbols())
+
+
+def test_strerror(lib):
+    from paper_1706_04552_amd import sg
+    for code in (sg.SG_OK, sg.SG_EINVAL, sg.SG_EALIAS, sg.SG_EHIP, sg.SG_ENOMEM, -99):
+        assert lib.sg_strerror(code)
+    assert b"overlap" in lib.sg_strerror(sg.SG_EALIAS)
+
+
+@pytest.mark.parametrize("r,rho", [(0, 1), (1, 2), (5, 1), (8, 16), (10, 32), (16, 4), (20, 1)])
+def test_lambda_grid_closed_form(r, rho):
+    from paper_1706_04552_amd import sg
+    rb = r - (rho.bit_length() - 1)
+    W, H = sg.sg_lambda_grid(r, rho)
+    assert (W, H) == (3 ** (rb // 2), 3 ** ((rb + 1) // 2))
+    assert sg.sg_block_count("lambda", r, rho) == 3 ** rb
+    assert sg.sg_block_count("bbox", r, rho) == 4 ** rb
+
+
+@pytest.mark.parametrize("r,rho", [(-1, 1), (21, 1), (3, 16), (5, 3), (5, 0), (8, 64), (8, -4)])
+def test_bad_shapes_are_rejected(lib, r, rho):
+    from paper_1706_04552_amd import sg
+    W, H, b = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.sg_lambda_grid(r, rho, ctypes.byref(W), ctypes.byref(H)) == sg.SG_EINVAL
+    assert lib.sg_block_count(0, r, rho, ctypes.byref(b)) == sg.SG_EINVAL
+    assert lib.sg_map_lambda(r, rho, fake, None) == sg.SG_EINVAL
+    assert lib.sg_map_bbox(r, rho, fake, None) == sg.SG_EINVAL
+    assert lib.sg_write_pass(0, r, rho, fake, 1, None) == sg.SG_EINVAL
+    assert lib.sg_ca_step(0, r, rho, fake, ctypes.c_void_p(0x7000000000), None) == sg.SG_EINVAL
+    assert lib.sg_diffuse_step(0, r, rho, fake, ctypes.c_void_p(0x7000000000), 0.2, None) == sg.SG_EINVAL
+
+
+def test_bad_map_kind_and_null_pointers(lib):
+    from paper_1706_04552_amd import sg
+    a, b = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x7000000000)
+    b64 = ctypes.c_uint64()
+    assert lib.sg_block_count(2, 4, 2, ctypes.byref(b64)) == sg.SG_EINVAL
+    assert lib.sg_block_count(0, 4, 2, None) == sg.SG_EINVAL
+    assert lib.sg_ca_step(2, 4, 2, a, b, None) == sg.SG_EINVAL
+    assert lib.sg_ca_step(-1, 4, 2, a, b, None) == sg.SG_EINVAL
+    assert lib.sg_ca_step(0, 4, 2, None, b, None) == sg.SG_EINVAL
+    assert lib.sg_ca_step(0, 4, 2, a, None, None) == sg.SG_EINVAL
+    assert lib.sg_diffuse_step(1, 4, 2, None, b, 0.2, None) == sg.SG_EINVAL
+    assert lib.sg_write_pass(0, 4, 2, None, 1, None) == sg.SG_EINVAL
+    assert lib.sg_map_lambda(4, 2, None, None) == sg.SG_EINVAL
+    assert lib.sg_map_lambda(4, 2, ctypes.c_void_p(0x10004), None) == sg.SG_EINVAL  # misaligned
+    assert lib.sg_map_bbox(4, 2, None, None) == sg.SG_EINVAL
+
+
+def test_overlapping_buffers_are_rejected(lib):
+    from paper_1706_04552_amd import sg
+    r = 4  # n*n = 256 bytes, 1024 for f32
+    base = 0x100000
+    a = ctypes.c_void_p(base)
+    for off in (0, 16, 240):
+        assert lib.sg_ca_step(0, r, 4, a, ctypes.c_void_p(base + off), None) == sg.SG_EALIAS
+        assert lib.sg_ca_step(1, r, 4, ctypes.c_void_p(base + off), a, None) == sg.SG_EALIAS
+    for off in (0, 16, 1008):
+        assert lib.sg_diffuse_step(0, r, 4, a, ctypes.c_void_p(base + off), 0.2, None) == sg.SG_EALIAS
+
+
+def test_python_binding_refuses_cpu_tensors():
+    import torch
+    from paper_1706_04552_amd import sg
+    a = torch.zeros(16 * 16, dtype=torch.uint8)
+    b = torch.zeros(16 * 16, dtype=torch.uint8)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        sg.sg_ca_step("lambda", 4, 4, a, b)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        sg.sg_write_pass("bbox", 4, 4, a, 1)
+
+
+def test_misaligned_state_arrays_are_rejected(lib):
+    from paper_1706_04552_amd import sg
+    a, b = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x7000000000)
+    for off in (1, 4, 8):
+        m = ctypes.c_void_p(0x7000000000 + off)
+        assert lib.sg_ca_step(0, 6, 4, a, m, None) == sg.SG_EINVAL
+        assert lib.sg_ca_step(0, 6, 4, m, b, None) == sg.SG_EINVAL
+        assert lib.sg_diffuse_step(0, 6, 4, a, m, 0.2, None) == sg.SG_EINVAL
+        assert lib.sg_write_pass(1, 6, 4, m, 1, None) == sg.SG_EINVAL

@@ -1,0 +1,226 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Bar: bit-exact for the block maps, the write pass and the uint8 life; for the
+FP32 diffusion, max-abs error <= 1e-5 * max|u_ref| and relative L2 error
+<= 1e-5 against the FP64 oracle.  Small cases compare every element and span
+several tiles with ragged tails; the full-size cases (r = 16 life, r = 14
+diffusion, in the launch configuration the benchmark times) compare sampled
+windows that the oracle evaluates from the dependency cone, plus properties
+that hold at any size.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1706_04552_amd import inputs, sg
+
+pytestmark = pytest.mark.gpu
+
+RHOS = [1, 2, 4, 8, 16, 32]
+DIFF_RTOL = 1e-5
+
+
+def note(msg):
+    print(f"[case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    sg.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(a: np.ndarray) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def gpu_ca(map_kind, r, rho, a0, steps):
+    a = dev(a0)
+    b = torch.zeros_like(a)
+    for _ in range(steps):
+        sg.sg_ca_step(map_kind, r, rho, a, b)
+        a, b = b, a
+    torch.cuda.synchronize()
+    return a
+
+
+def gpu_diffuse(map_kind, r, rho, u0, steps, alpha=0.2):
+    a = dev(u0)
+    b = torch.zeros_like(a)
+    for _ in range(steps):
+        sg.sg_diffuse_step(map_kind, r, rho, a, b, alpha)
+        a, b = b, a
+    torch.cuda.synchronize()
+    return a
+
+
+def diff_errors(got: np.ndarray, ref: np.ndarray):
+    d = got.astype(np.float64) - ref
+    max_abs = float(np.abs(d).max()) if d.size else 0.0
+    scale = float(np.abs(ref).max()) if ref.size else 0.0
+    rel_l2 = float(np.linalg.norm(d) / max(np.linalg.norm(ref), 1e-300))
+    return max_abs, scale, rel_l2
+
+
+def cases(rs, rhos=RHOS):
+    return [(r, rho) for r in rs for rho in rhos if rho <= (1 << r)]
+
+
+# ------------------------------------------------------------------ maps
+
+@pytest.mark.parametrize("r,rho", [(0, 1), (1, 1), (1, 2), (3, 2), (5, 4), (6, 1), (8, 16),
+                                   (9, 8), (10, 32), (12, 1), (13, 2), (15, 32)])
+def test_map_lambda_exact(r, rho):
+    rb = r - (rho.bit_length() - 1)
+    note(f"map_lambda r={r} rho={rho}")
+    d = torch.zeros(2 * 3 ** rb, dtype=torch.int32, device="cuda")
+    sg.sg_map_lambda(r, rho, d)
+    got = d.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    assert np.array_equal(got, O.map_lambda(rb))
+
+
+def test_map_lambda_sampled_r16_rho1():
+    r, rho, rb = 16, 1, 16
+    note("map_lambda r=16 rho=1 sampled")
+    d = torch.zeros(2 * 3 ** rb, dtype=torch.int32, device="cuda")
+    sg.sg_map_lambda(r, rho, d)
+    got = d.cpu().numpy().view(np.uint32).reshape(-1, 2).astype(np.int64)
+    W, _ = O.lambda_grid(rb)
+    nb = 1 << rb
+    rng = np.random.default_rng(7)
+    for i in list(rng.integers(0, 3 ** rb, size=3000)) + [0, 3 ** rb - 1]:
+        lx, ly = O.lambda_paper(rb, int(i % W), int(i // W))
+        assert (got[i, 0], got[i, 1]) == (lx, nb - 1 - ly), i
+    assert np.all((got[:, 0] & got[:, 1]) == 0)
+    assert len(np.unique(got[:, 1] * nb + got[:, 0])) == 3 ** rb
+
+
+@pytest.mark.parametrize("r,rho", [(0, 1), (2, 1), (4, 2), (7, 4), (9, 16), (10, 32), (11, 8)])
+def test_map_bbox_exact(r, rho):
+    note(f"map_bbox r={r} rho={rho}")
+    nb = (1 << r) // rho
+    d = torch.full((nb * nb,), 9, dtype=torch.uint8, device="cuda")
+    sg.sg_map_bbox(r, rho, d)
+    assert np.array_equal(d.cpu().numpy().reshape(nb, nb), O.map_bbox(r, rho))
+
+
+# ------------------------------------------------------------------ write pass
+
+@pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
+@pytest.mark.parametrize("r,rho", cases([0, 1, 3, 6, 9, 11]))
+def test_write_pass_exact(map_kind, r, rho):
+    note(f"write_pass {map_kind} r={r} rho={rho}")
+    n = 1 << r
+    for v in (1, 255):
+        a = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+        sg.sg_write_pass(map_kind, r, rho, a, v)
+        assert np.array_equal(a.cpu().numpy(), O.write_pass(r, v))
+
+
+# ------------------------------------------------------------------ life
+
+@pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
+@pytest.mark.parametrize("r,rho", cases([0, 1, 2, 3, 5, 7, 10]))
+def test_ca_exact_small(map_kind, r, rho):
+    note(f"ca {map_kind} r={r} rho={rho} 10 steps")
+    a0 = inputs.bernoulli_state(r, 0.5, 1706 + r)
+    got = gpu_ca(map_kind, r, rho, a0, 10).cpu().numpy()
+    assert np.array_equal(got, O.life_steps(r, a0, 10))
+
+
+@pytest.mark.parametrize("map_kind,rho", [("lambda", 4), ("lambda", 8), ("lambda", 16),
+                                          ("lambda", 32), ("bbox", 16), ("bbox", 32)])
+def test_ca_exact_r12_100_steps(map_kind, rho):
+    r = 12
+    note(f"ca {map_kind} r=12 rho={rho} 100 steps")
+    a0 = inputs.bernoulli_state(r, 0.5, 1706)
+    got = gpu_ca(map_kind, r, rho, a0, 100).cpu().numpy()
+    ref = _r12_reference(a0)
+    assert np.array_equal(got, ref)
+    xr, pop = O.row_checksums(r, ref)
+    assert pop.sum() > 0  # the state has not died out
+
+
+_R12_REF = {}
+
+
+def _r12_reference(a0):
+    if "ref" not in _R12_REF:
+        _R12_REF["ref"] = O.life_steps(12, a0, 100)
+    return _R12_REF["ref"]
+
+
+def _windows(n, rng, count, w, h):
+    wins = [(0, 0), (n - w, 0), (0, n - h), (n // 2 - w // 2, n // 2 - h // 2)]
+    wins += [(int(rng.integers(0, n - w)), int(rng.integers(0, n - h))) for _ in range(count)]
+    return wins
+
+
+@pytest.mark.parametrize("r,rho", [(14, 16), (16, 16)])
+def test_ca_full_size_sampled(r, rho):
+    steps = 100
+    note(f"ca full-size r={r} rho={rho} {steps} steps")
+    n = 1 << r
+    a0 = inputs.bernoulli_state(r, 0.5, 1706)
+    lam = gpu_ca("lambda", r, rho, a0, steps)
+    bb = gpu_ca("bbox", r, rho, a0, steps)
+    assert torch.equal(lam, bb)
+    del bb
+    got = lam.cpu().numpy()
+    del lam
+    rng = np.random.default_rng(r)
+    for (x0, y0) in _windows(n, rng, 6, 64, 16):
+        ref = O.life_window(r, a0, x0, y0, 64, 16, steps)
+        assert np.array_equal(got[y0:y0 + 16, x0:x0 + 64], ref), (x0, y0)
+    # properties at any size: 0/1 values, nothing off the gasket
+    assert got.max() <= 1
+    for y0 in range(0, n, max(1, (1 << 24) // n)):
+        y1 = min(n, y0 + max(1, (1 << 24) // n))
+        assert not got[y0:y1][~inputs.gasket_rows(n, y0, y1)].any()
+
+
+# ------------------------------------------------------------------ diffusion
+
+@pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
+@pytest.mark.parametrize("r,rho", cases([0, 1, 2, 4, 6, 9]))
+def test_diffusion_small(map_kind, r, rho):
+    steps = 50
+    note(f"diffuse {map_kind} r={r} rho={rho} {steps} steps")
+    u0 = inputs.uniform_field(r, 1706 + r)
+    got = gpu_diffuse(map_kind, r, rho, u0, steps).cpu().numpy()
+    ref = O.diffuse_steps(r, u0, steps)
+    max_abs, scale, rel_l2 = diff_errors(got, ref)
+    assert max_abs <= DIFF_RTOL * scale
+    assert rel_l2 <= DIFF_RTOL
+    assert np.all(got[ref == 0.0] == 0.0)
+
+
+def test_diffusion_full_size_sampled():
+    r, rho, steps = 14, 16, 500
+    note(f"diffuse full-size r={r} rho={rho} {steps} steps")
+    n = 1 << r
+    u0 = inputs.uniform_field(r, 1706)
+    lam = gpu_diffuse("lambda", r, rho, u0, steps)
+    bb = gpu_diffuse("bbox", r, rho, u0, steps)
+    assert torch.equal(lam, bb)
+    del bb
+    got = lam.cpu().numpy()
+    del lam
+    rng = np.random.default_rng(3)
+    refs, gots = [], []
+    for (x0, y0) in _windows(n, rng, 2, 8, 8):
+        refs.append(O.diffuse_window(r, u0, x0, y0, 8, 8, steps))
+        gots.append(got[y0:y0 + 8, x0:x0 + 8])
+    max_abs, scale, rel_l2 = diff_errors(np.concatenate(gots), np.concatenate(refs))
+    note(f"diffuse r=14 sampled: max_abs={max_abs:.3e} scale={scale:.3e} rel_l2={rel_l2:.3e}")
+    assert max_abs <= DIFF_RTOL * scale
+    assert rel_l2 <= DIFF_RTOL
+    # the total is conserved by the scheme (exactly in real arithmetic)
+    t0 = float(u0.astype(np.float64).sum())
+    t1 = float(got.astype(np.float64).sum())
+    assert abs(t1 - t0) <= DIFF_RTOL * t0
