@@ -27,7 +27,7 @@ sys.path.insert(0, HERE)
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 CA_BYTES_PER_CELL = 2          # read own state once, write it once
 WRITE_BYTES_PER_CELL = 1       # store the constant once
-RHOS = (4, 8, 16, 32)
+RHOS = (4, 8, 16, 32, 64, 128, 256)
 R = 16
 SEED = 1706
 PAPER_BEST_VS_BEST = "about 10x (best lambda, rho=16, vs best bounding box, rho=32; Titan-X Pascal GP102; write pass at n=2^16)"
@@ -69,17 +69,23 @@ def traffic_from_profile(kernel_tag):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(r, a0_host):
-    """The oracle, as it stands, on a bounded sample: one generation of the
-    same r = 16 state, on the host's cores."""
+def cpu_baseline(r, a0_host, min_seconds=10.0, max_gens=100):
+    """The oracle, as it stands, on a bounded sample: generations of the same
+    r = 16 state on the host's cores, until about `min_seconds` have passed."""
     import oracle as O
     threads = O.threads()
+    cur = a0_host
+    gens = 0
     t0 = time.perf_counter()
-    O.life_step(r, a0_host)
-    dt = time.perf_counter() - t0
-    return {"value": 3 ** r / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"1 generation of the r={r} gasket ({3 ** r} cells), dense C oracle, "
-                      f"{dt:.2f} s wall"}
+    while True:
+        cur = O.life_step(r, cur)
+        gens += 1
+        dt = time.perf_counter() - t0
+        if dt >= min_seconds or gens >= max_gens:
+            break
+    return {"value": gens * 3 ** r / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"{gens} generations of the r={r} gasket ({3 ** r} cells each) from the "
+                      f"benchmark's initial state, dense C oracle, {dt:.1f} s wall"}
 
 
 def main():
@@ -89,6 +95,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--rho", type=int, nargs="*", default=list(RHOS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
@@ -108,6 +116,13 @@ def main():
     A = torch.from_numpy(a0).to(dev)
     B = torch.zeros_like(A)
     torch.cuda.synchronize()
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        ms = time_region(torch, lambda: dst.copy_(src), 5, 1)
+        log(f"copy calibration: 1 GiB in {ms * 1e3:.1f} us = {2 * (1 << 30) / (ms * 1e-3) / 1e9:.0f} GB/s")
+        del src, dst
 
     results = {"lambda": {}, "bbox": {}}
     for map_kind in ("lambda", "bbox"):
@@ -153,7 +168,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle (1 generation at r=16)")
+        log("timing the CPU oracle (r=16 generations, >= 10 s)")
         cpu = cpu_baseline(R, a0)
 
     prop = torch.cuda.get_device_properties(0)

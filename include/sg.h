@@ -51,7 +51,7 @@ extern "C" {
 #define SG_API __attribute__((visibility("default")))
 
 #define SG_MAX_R 20
-#define SG_MAX_RHO 32
+#define SG_MAX_RHO 256
 
 typedef enum sg_status {
     SG_OK = 0,

@@ -9,7 +9,16 @@
 //           under the identity (bx, by) = (t mod n_b, t div n_b) and discards
 //           the tile's lanes unless bx & by == 0: 4^r_b tiles.
 // Inside a fractal tile the lanes use bounding sub-boxes (Section III-D):
-// every lane keeps its row and masks cells with (tx & ty) != 0.
+// every lane keeps its cells and masks those with (tx & ty) != 0.
+//
+// Two lane layouts:
+//   rows  (rho <= 16): one lane per tile row, 64/rho tiles per wave; the rows
+//         above/below come from the neighbouring lanes (DPP wave shifts).
+//   strip (rho >= 32): lanes run along x in 16-byte chunks, so one wave
+//         instruction covers whole 128-byte lines of a tile row; each lane
+//         walks down a band of 16 rows holding the band plus its two halo rows
+//         in registers, and the left/right neighbour cells of interior chunks
+//         come from the adjacent lanes (DPP wave shifts).
 #include "sg_device.h"
 #include "sg_launch.h"
 
@@ -280,6 +289,177 @@ __global__ __launch_bounds__(kWG) void k_diffuse(const float *__restrict__ in,
   store_frow<RHO>(out + y * n + X0, O);
 }
 
+
+// ------------------------------------------------------------------ strip layout
+
+constexpr int kBand = 16;  // rows per lane band in the strip layout
+
+// HBM stores below a 64-byte granule cost a read-modify-write, and sparse
+// reads run fastest as whole 128-byte lines.  When a tile row spans whole
+// granules (rho >= 64 bytes), the strip kernels store every 64-byte granule
+// that holds a gasket cell in full (0 on its off-gasket cells) and load every
+// 128-byte line (or the whole row, if shorter) that holds one.  A granule that
+// holds a gasket cell is exactly one whose first cell does: x0 & y == 0 for a
+// granule starting at x0 (a multiple of its size).
+template <int ROW_BYTES>
+struct Granules {
+  static constexpr int STORE = ROW_BYTES >= 64 ? 64 : 16;
+  static constexpr int LOAD = ROW_BYTES >= 128 ? 128 : (ROW_BYTES >= 64 ? 64 : 16);
+};
+
+template <int RHO, int CHUNK>
+struct Strip {
+  static constexpr int CPR = RHO / CHUNK;         // chunks per tile row
+  static constexpr int LPT = CPR * (RHO / kBand); // lanes per tile
+  static constexpr int WGS = LPT > kWG ? LPT : kWG;
+  static constexpr int TPG = WGS / LPT;           // tiles per workgroup
+};
+
+template <int RHO, bool LAMBDA>
+__global__ __launch_bounds__((Strip<RHO, 16>::WGS)) void k_write_strip(
+    uint8_t *__restrict__ a, int r, int rb, uint64_t tile_base, uint64_t ntiles,
+    uint32_t value) {
+  using G = Strip<RHO, 16>;
+  const int slot = threadIdx.x / G::LPT, lt = threadIdx.x % G::LPT;
+  const int band = lt / G::CPR, c = lt % G::CPR;
+  uint32_t bx, by;
+  if (!tile_of<LAMBDA>(tile_base, ntiles, G::TPG, slot, rb, bx, by)) return;
+  const size_t n = (size_t)1 << r;
+  const size_t x = (size_t)bx * RHO + 16 * c;
+  const size_t y0 = (size_t)by * RHO + (size_t)band * kBand;
+#pragma unroll
+  for (int i = 0; i < kBand; ++i) {
+    const size_t y = y0 + i;
+    constexpr size_t gmask = ~(size_t)(Granules<RHO>::STORE - 1);
+    if (((x & gmask) & y) != 0) continue;  // no gasket cell in this granule
+    // cells of this chunk are on the gasket iff x & y == 0 and (i & y) == 0
+    const uint32_t v = (x & y) == 0 ? value : 0u;
+    U8Row<16> row;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) row.w[k] = row_mask_word<16>(k, (uint32_t)(y & 15)) * v;
+    store_row<16>(a + y * n + x, row);
+  }
+}
+
+template <int RHO, bool LAMBDA>
+__global__ __launch_bounds__((Strip<RHO, 16>::WGS)) void k_life_strip(
+    const uint8_t *__restrict__ in, uint8_t *__restrict__ out, int r, int rb,
+    uint64_t tile_base, uint64_t ntiles) {
+  using G = Strip<RHO, 16>;
+  const int slot = threadIdx.x / G::LPT, lt = threadIdx.x % G::LPT;
+  const int band = lt / G::CPR, c = lt % G::CPR;
+  uint32_t bx, by;
+  if (!tile_of<LAMBDA>(tile_base, ntiles, G::TPG, slot, rb, bx, by)) return;
+  const size_t n = (size_t)1 << r;
+  const size_t X0 = (size_t)bx * RHO, Y0 = (size_t)by * RHO;
+  const size_t x = X0 + 16 * c;
+  const size_t y0 = Y0 + (size_t)band * kBand;
+  const bool left_edge = c == 0, right_edge = c == G::CPR - 1;
+  const bool has_l = X0 > 0, has_r = X0 + RHO < n;
+  const size_t xl = X0 - 1, xr = X0 + RHO;
+
+  // the band's rows y0 .. y0+15 and the halo rows y0-1, y0+16
+  U8Row<16> w[kBand + 2];
+  uint32_t hl[kBand + 2], hr[kBand + 2];
+#pragma unroll
+  for (int i = 0; i < kBand + 2; ++i) {
+    const bool ok = (i > 0 || y0 > 0) && (i < kBand + 1 || y0 + kBand < n);
+    const size_t yy = y0 + i - 1;
+    zero_row<16>(w[i]);
+    hl[i] = hr[i] = 0u;
+    constexpr size_t lmask = ~(size_t)(Granules<RHO>::LOAD - 1);
+    if (ok && ((x & lmask) & yy) == 0) load_row<16>(w[i], in + yy * n + x);
+    if (left_edge && ok && has_l && (xl & yy) == 0) hl[i] = in[yy * n + xl];
+    if (right_edge && ok && has_r && (xr & yy) == 0) hr[i] = in[yy * n + xr];
+  }
+#pragma unroll
+  for (int i = 1; i <= kBand; ++i) {
+    const size_t y = y0 + i - 1;
+    U8Row<16> V, L, R, O;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) V.w[k] = w[i - 1].w[k] + w[i].w[k] + w[i + 1].w[k];
+    const uint32_t from_l = from_prev_lane(V.w[3]) >> 24;   // byte 15 of chunk c-1
+    const uint32_t from_r = from_next_lane(V.w[0]) & 0xffu;  // byte 0 of chunk c+1
+    const uint32_t vl = left_edge ? hl[i - 1] + hl[i] + hl[i + 1] : from_l;
+    const uint32_t vr = right_edge ? hr[i - 1] + hr[i] + hr[i + 1] : from_r;
+    shift_in_left<16>(L, V, vl);
+    shift_in_right<16>(R, V, vr);
+    const uint32_t ym = (uint32_t)(y & 15);
+    const uint32_t chunk_on = (x & y) == 0 ? ~0u : 0u;  // chunk holds gasket cells
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t cnt = L.w[k] + V.w[k] + R.w[k] - w[i].w[k];
+      const uint32_t xx = (cnt | w[i].w[k]) ^ 0x03030303u;
+      uint32_t z = xx | (xx >> 1);
+      z |= z >> 2;
+      O.w[k] = ~z & row_mask_word<16>(k, ym) & chunk_on;
+    }
+    constexpr size_t smask = ~(size_t)(Granules<RHO>::STORE - 1);
+    if (((x & smask) & y) == 0) store_row<16>(out + y * n + x, O);
+  }
+}
+
+template <int RHO, bool LAMBDA>
+__global__ __launch_bounds__((Strip<RHO, 4>::WGS)) void k_diffuse_strip(
+    const float *__restrict__ in, float *__restrict__ out, int r, int rb,
+    uint64_t tile_base, uint64_t ntiles, float alpha) {
+  using G = Strip<RHO, 4>;
+  const int slot = threadIdx.x / G::LPT, lt = threadIdx.x % G::LPT;
+  const int band = lt / G::CPR, c = lt % G::CPR;
+  uint32_t bx, by;
+  if (!tile_of<LAMBDA>(tile_base, ntiles, G::TPG, slot, rb, bx, by)) return;
+  const size_t n = (size_t)1 << r;
+  const size_t X0 = (size_t)bx * RHO, Y0 = (size_t)by * RHO;
+  const size_t x = X0 + 4 * c;
+  const size_t y0 = Y0 + (size_t)band * kBand;
+  const bool left_edge = c == 0, right_edge = c == G::CPR - 1;
+  const bool has_l = X0 > 0, has_r = X0 + RHO < n;
+  const size_t xl = X0 - 1, xr = X0 + RHO;
+
+  F32Row<4> w[kBand + 2];
+  float hl[kBand + 2], hr[kBand + 2];
+#pragma unroll
+  for (int i = 0; i < kBand + 2; ++i) {
+    const bool ok = (i > 0 || y0 > 0) && (i < kBand + 1 || y0 + kBand < n);
+    const size_t yy = y0 + i - 1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[i].v[j] = 0.0f;
+    hl[i] = hr[i] = 0.0f;
+    constexpr size_t lmask = ~(size_t)(Granules<4 * RHO>::LOAD / 4 - 1);
+    if (ok && ((x & lmask) & yy) == 0) load_frow<4>(w[i], in + yy * n + x);
+    if (left_edge && ok && has_l && (xl & yy) == 0) hl[i] = in[yy * n + xl];
+    if (right_edge && ok && has_r && (xr & yy) == 0) hr[i] = in[yy * n + xr];
+  }
+#pragma unroll
+  for (int i = 1; i <= kBand; ++i) {
+    const size_t y = y0 + i - 1;
+    const float from_l = from_prev_lane(w[i].v[3]);
+    const float from_r = from_next_lane(w[i].v[0]);
+    const float west0 = left_edge ? hl[i] : from_l;
+    const float east3 = right_edge ? hr[i] : from_r;
+    F32Row<4> O;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const size_t xj = x + j;
+      const float u = w[i].v[j];
+      const float west = j == 0 ? west0 : w[i].v[j - 1];
+      const float east = j == 3 ? east3 : w[i].v[j + 1];
+      const bool mw = xj > 0 && on_gasket(xj - 1, y);
+      const bool me = xj + 1 < n && on_gasket(xj + 1, y);
+      const bool mn = y > 0 && on_gasket(xj, y - 1);
+      const bool ms = y + 1 < n && on_gasket(xj, y + 1);
+      float s = 0.0f;
+      s += mw ? (west - u) : 0.0f;
+      s += me ? (east - u) : 0.0f;
+      s += mn ? (w[i - 1].v[j] - u) : 0.0f;
+      s += ms ? (w[i + 1].v[j] - u) : 0.0f;
+      O.v[j] = on_gasket(xj, y) ? u + alpha * s : 0.0f;
+    }
+    constexpr size_t smask = ~(size_t)(Granules<4 * RHO>::STORE / 4 - 1);
+    if (((x & smask) & y) == 0) store_frow<4>(out + y * n + x, O);
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 
 // HIP bounds gridDim.x * blockDim.x below 2^32; launches are split into
@@ -289,13 +469,47 @@ constexpr uint64_t kMaxGroupsPerLaunch = 1ull << 23;
 template <typename F>
 hipError_t launch_tiles(uint64_t ntiles, int tpg, hipStream_t s, F &&launch_one) {
   const uint64_t groups = (ntiles + tpg - 1) / tpg;
-  for (uint64_t g0 = 0; g0 < groups; g0 += kMaxGroupsPerLaunch) {
-    const uint64_t g = groups - g0 < kMaxGroupsPerLaunch ? groups - g0 : kMaxGroupsPerLaunch;
+  const uint64_t per_launch = kMaxGroupsPerLaunch / 4;  // up to 1024 threads per group
+  for (uint64_t g0 = 0; g0 < groups; g0 += per_launch) {
+    const uint64_t g = groups - g0 < per_launch ? groups - g0 : per_launch;
     launch_one(dim3((unsigned)g), g0 * (uint64_t)tpg, s);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+template <int RHO>
+hipError_t write_strip(const PassArgs &a, uint8_t *d, uint32_t value) {
+  using G = Strip<RHO, 16>;
+  return launch_tiles(a.ntiles, G::TPG, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
+    if (a.lambda)
+      hipLaunchKernelGGL((k_write_strip<RHO, true>), grid, dim3(G::WGS), 0, s, d, a.r, a.rb, base, a.ntiles, value);
+    else
+      hipLaunchKernelGGL((k_write_strip<RHO, false>), grid, dim3(G::WGS), 0, s, d, a.r, a.rb, base, a.ntiles, value);
+  });
+}
+
+template <int RHO>
+hipError_t life_strip(const PassArgs &a, const uint8_t *in, uint8_t *out) {
+  using G = Strip<RHO, 16>;
+  return launch_tiles(a.ntiles, G::TPG, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
+    if (a.lambda)
+      hipLaunchKernelGGL((k_life_strip<RHO, true>), grid, dim3(G::WGS), 0, s, in, out, a.r, a.rb, base, a.ntiles);
+    else
+      hipLaunchKernelGGL((k_life_strip<RHO, false>), grid, dim3(G::WGS), 0, s, in, out, a.r, a.rb, base, a.ntiles);
+  });
+}
+
+template <int RHO>
+hipError_t diffuse_strip(const PassArgs &a, const float *in, float *out, float alpha) {
+  using G = Strip<RHO, 4>;
+  return launch_tiles(a.ntiles, G::TPG, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
+    if (a.lambda)
+      hipLaunchKernelGGL((k_diffuse_strip<RHO, true>), grid, dim3(G::WGS), 0, s, in, out, a.r, a.rb, base, a.ntiles, alpha);
+    else
+      hipLaunchKernelGGL((k_diffuse_strip<RHO, false>), grid, dim3(G::WGS), 0, s, in, out, a.r, a.rb, base, a.ntiles, alpha);
+  });
 }
 
 template <int RHO>
@@ -351,7 +565,10 @@ hipError_t launch_write(const PassArgs &a, uint8_t *d, uint8_t value) {
     case 4: return write_rho<4>(a, d, value);
     case 8: return write_rho<8>(a, d, value);
     case 16: return write_rho<16>(a, d, value);
-    case 32: return write_rho<32>(a, d, value);
+    case 32: return write_strip<32>(a, d, value);
+    case 64: return write_strip<64>(a, d, value);
+    case 128: return write_strip<128>(a, d, value);
+    case 256: return write_strip<256>(a, d, value);
     default: return hipErrorInvalidValue;
   }
 }
@@ -363,7 +580,10 @@ hipError_t launch_life(const PassArgs &a, const uint8_t *in, uint8_t *out) {
     case 4: return life_rho<4>(a, in, out);
     case 8: return life_rho<8>(a, in, out);
     case 16: return life_rho<16>(a, in, out);
-    case 32: return life_rho<32>(a, in, out);
+    case 32: return life_strip<32>(a, in, out);
+    case 64: return life_strip<64>(a, in, out);
+    case 128: return life_strip<128>(a, in, out);
+    case 256: return life_strip<256>(a, in, out);
     default: return hipErrorInvalidValue;
   }
 }
@@ -375,7 +595,10 @@ hipError_t launch_diffuse(const PassArgs &a, const float *in, float *out, float 
     case 4: return diffuse_rho<4>(a, in, out, alpha);
     case 8: return diffuse_rho<8>(a, in, out, alpha);
     case 16: return diffuse_rho<16>(a, in, out, alpha);
-    case 32: return diffuse_rho<32>(a, in, out, alpha);
+    case 32: return diffuse_strip<32>(a, in, out, alpha);
+    case 64: return diffuse_strip<64>(a, in, out, alpha);
+    case 128: return diffuse_strip<128>(a, in, out, alpha);
+    case 256: return diffuse_strip<256>(a, in, out, alpha);
     default: return hipErrorInvalidValue;
   }
 }

@@ -16,7 +16,7 @@ from . import build as _build
 
 SG_OK, SG_EINVAL, SG_EALIAS, SG_EHIP, SG_ENOMEM = 0, -1, -2, -3, -4
 SG_MAP_LAMBDA, SG_MAP_BBOX = 0, 1
-SG_MAX_R, SG_MAX_RHO = 20, 32
+SG_MAX_R, SG_MAX_RHO = 20, 256
 MAPS = {"lambda": SG_MAP_LAMBDA, "bbox": SG_MAP_BBOX}
 
 # Every symbol declared in include/sg.h, with its ctypes signature.

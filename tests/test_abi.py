@@ -65,7 +65,7 @@ def test_lambda_grid_closed_form(r, rho):
     assert sg.sg_block_count("bbox", r, rho) == 4 ** rb
 
 
-@pytest.mark.parametrize("r,rho", [(-1, 1), (21, 1), (3, 16), (5, 3), (5, 0), (8, 64), (8, -4)])
+@pytest.mark.parametrize("r,rho", [(-1, 1), (21, 1), (3, 16), (5, 3), (5, 0), (8, 512), (7, 256), (8, -4)])
 def test_bad_shapes_are_rejected(lib, r, rho):
     from paper_1706_04552_amd import sg
     W, H, b = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()

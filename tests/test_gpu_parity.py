@@ -19,7 +19,7 @@ from paper_1706_04552_amd import inputs, sg
 
 pytestmark = pytest.mark.gpu
 
-RHOS = [1, 2, 4, 8, 16, 32]
+RHOS = [1, 2, 4, 8, 16, 32, 64, 128, 256]
 DIFF_RTOL = 1e-5
 
 
@@ -134,7 +134,8 @@ def test_ca_exact_small(map_kind, r, rho):
 
 
 @pytest.mark.parametrize("map_kind,rho", [("lambda", 4), ("lambda", 8), ("lambda", 16),
-                                          ("lambda", 32), ("bbox", 16), ("bbox", 32)])
+                                          ("lambda", 32), ("lambda", 128), ("lambda", 256),
+                                          ("bbox", 16), ("bbox", 128)])
 def test_ca_exact_r12_100_steps(map_kind, rho):
     r = 12
     note(f"ca {map_kind} r=12 rho={rho} 100 steps")
@@ -161,7 +162,7 @@ def _windows(n, rng, count, w, h):
     return wins
 
 
-@pytest.mark.parametrize("r,rho", [(14, 16), (16, 16)])
+@pytest.mark.parametrize("r,rho", [(14, 16), (16, 16), (16, 128)])
 def test_ca_full_size_sampled(r, rho):
     steps = 100
     note(f"ca full-size r={r} rho={rho} {steps} steps")
@@ -200,8 +201,9 @@ def test_diffusion_small(map_kind, r, rho):
     assert np.all(got[ref == 0.0] == 0.0)
 
 
-def test_diffusion_full_size_sampled():
-    r, rho, steps = 14, 16, 500
+@pytest.mark.parametrize("rho", [16, 64])
+def test_diffusion_full_size_sampled(rho):
+    r, steps = 14, 500
     note(f"diffuse full-size r={r} rho={rho} {steps} steps")
     n = 1 << r
     u0 = inputs.uniform_field(r, 1706)
