@@ -115,6 +115,26 @@ SG_API int sg_write_pass(int map, int r, int rho, uint8_t *d_a, uint8_t value,
 SG_API int sg_ca_step(int map, int r, int rho, const uint8_t *d_in,
                       uint8_t *d_out, void *stream);
 
+/* `steps` generations of the life step above (sg_ca_step), with the result
+ * left in d_out.  The generations run in passes of up to `steps_per_pass`
+ * generations each: a pass reads its tile plus a halo of that many cells
+ * from HBM once, runs the generations on chip and writes the tile once
+ * (temporal blocking), so HBM traffic per generation falls by that factor.
+ * The result is identical to `steps` calls of sg_ca_step.
+ *   steps_per_pass: 1 (one launch per generation, any rho), 2..16 (rho in
+ *     {64, 128, 256}), or 0 for the library's choice (16 where supported,
+ *     else 1).
+ *   d_in: read only.  d_out: receives the state after `steps` generations.
+ *   d_work: a third n * n buffer used when more than one pass runs (may be
+ *     NULL otherwise).  All three: device, 16-byte aligned, pairwise
+ *     non-overlapping, 0 on every cell off the gasket.
+ *   steps = 0 copies d_in to d_out.
+ * Errors: SG_EINVAL (bad sizes, steps < 0, unsupported steps_per_pass for
+ * rho, d_work missing when needed), SG_EALIAS, SG_EHIP. */
+SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
+                       const uint8_t *d_in, uint8_t *d_out, uint8_t *d_work,
+                       void *stream);
+
 /* One explicit diffusion step on the gasket in FP32 (a nearest-neighbour
  * application, Section I): for every gasket cell,
  *   out = u + alpha * sum_{nb in W, E, N, S; in grid and in gasket} (u_nb - u),

@@ -126,6 +126,38 @@ SG_API int sg_ca_step(int map, int r, int rho, const uint8_t *d_in, uint8_t *d_o
   return hip_status(sg::launch_life(a, d_in, d_out));
 }
 
+SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
+                       const uint8_t *d_in, uint8_t *d_out, uint8_t *d_work, void *stream) {
+  sg::PassArgs a;
+  const int st = pass_args(map, r, rho, stream, a);
+  if (st != SG_OK) return st;
+  if (steps < 0 || steps_per_pass < 0 || steps_per_pass > sg::kMaxStepsPerPass) return SG_EINVAL;
+  const bool tb_ok = sg::life_tb_supported(rho);
+  if (steps_per_pass == 0) steps_per_pass = tb_ok ? sg::kMaxStepsPerPass : 1;
+  if (steps_per_pass > 1 && !tb_ok) return SG_EINVAL;
+  if (!d_in || !d_out || misaligned(d_in) || misaligned(d_out)) return SG_EINVAL;
+  const size_t bytes = ((size_t)1 << r) * ((size_t)1 << r);
+  if (overlaps(d_in, d_out, bytes)) return SG_EALIAS;
+  const int passes = (steps + steps_per_pass - 1) / steps_per_pass;
+  if (passes >= 2) {
+    if (!d_work || misaligned(d_work)) return SG_EINVAL;
+    if (overlaps(d_work, d_in, bytes) || overlaps(d_work, d_out, bytes)) return SG_EALIAS;
+  }
+  if (steps == 0)
+    return hip_status(hipMemcpyAsync(d_out, d_in, bytes, hipMemcpyDeviceToDevice, a.stream));
+  // the last pass must land in d_out: alternate d_out / d_work backwards
+  const uint8_t *src = d_in;
+  for (int k = 1; k <= passes; ++k) {
+    uint8_t *dst = ((passes - k) % 2 == 0) ? d_out : d_work;
+    const int T = k < passes ? steps_per_pass : steps - (passes - 1) * steps_per_pass;
+    const hipError_t e = T == 1 && steps_per_pass == 1 ? sg::launch_life(a, src, dst)
+                                                       : sg::launch_life_tb(a, T, src, dst);
+    if (e != hipSuccess) return hip_status(e);
+    src = dst;
+  }
+  return SG_OK;
+}
+
 SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in, float *d_out,
                            float alpha, void *stream) {
   sg::PassArgs a;

@@ -23,4 +23,10 @@ hipError_t launch_write(const PassArgs &a, uint8_t *d, uint8_t value);
 hipError_t launch_life(const PassArgs &a, const uint8_t *in, uint8_t *out);
 hipError_t launch_diffuse(const PassArgs &a, const float *in, float *out, float alpha);
 
+// Temporally blocked life: T generations per pass, T in [1, kMaxStepsPerPass],
+// for tile sides rho in {64, 128, 256}.
+constexpr int kMaxStepsPerPass = 16;
+bool life_tb_supported(int rho);
+hipError_t launch_life_tb(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
+
 }  // namespace sg

@@ -33,6 +33,9 @@ _SIGNATURES = {
                                      ctypes.c_uint8, ctypes.c_void_p]),
     "sg_ca_step": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_ca_steps": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
     "sg_diffuse_step": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
 }
@@ -158,6 +161,19 @@ def sg_ca_step(map_kind, r: int, rho: int, d_in: torch.Tensor, d_out: torch.Tens
     pi = _dev(d_in, torch.uint8, n2, "d_in")
     po = _dev(d_out, torch.uint8, n2, "d_out")
     _check(load().sg_ca_step(_map(map_kind), r, rho, pi, po, _stream(stream)), "sg_ca_step")
+    return d_out
+
+
+def sg_ca_steps(map_kind, r: int, rho: int, steps: int, d_in: torch.Tensor,
+                d_out: torch.Tensor, d_work: Optional[torch.Tensor] = None,
+                steps_per_pass: int = 0, stream=None) -> torch.Tensor:
+    """`steps` life generations from d_in into d_out (d_work: third buffer)."""
+    n2 = _n2(r)
+    pi = _dev(d_in, torch.uint8, n2, "d_in")
+    po = _dev(d_out, torch.uint8, n2, "d_out")
+    pw = _dev(d_work, torch.uint8, n2, "d_work") if d_work is not None else None
+    _check(load().sg_ca_steps(_map(map_kind), r, rho, steps, steps_per_pass, pi, po, pw,
+                              _stream(stream)), "sg_ca_steps")
     return d_out
 
 

@@ -128,3 +128,24 @@ def test_misaligned_state_arrays_are_rejected(lib):
         assert lib.sg_ca_step(0, 6, 4, m, b, None) == sg.SG_EINVAL
         assert lib.sg_diffuse_step(0, 6, 4, a, m, 0.2, None) == sg.SG_EINVAL
         assert lib.sg_write_pass(1, 6, 4, m, 1, None) == sg.SG_EINVAL
+
+
+def test_ca_steps_validation(lib):
+    from paper_1706_04552_amd import sg
+    a, b, w = (ctypes.c_void_p(0x100000), ctypes.c_void_p(0x7000000000),
+               ctypes.c_void_p(0x7100000000))
+    r = 8  # n*n = 65536 bytes
+    # steps_per_pass out of range, or > 1 where the tile side has no temporal blocking
+    assert lib.sg_ca_steps(0, r, 64, 10, 17, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 64, 10, -1, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 16, 10, 4, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 32, 10, 2, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 64, -1, 4, a, b, w, None) == sg.SG_EINVAL
+    # more than one pass needs a work buffer, distinct from in and out
+    assert lib.sg_ca_steps(0, r, 64, 17, 16, a, b, None, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 16, 2, 1, a, b, None, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 64, 17, 16, a, b, ctypes.c_void_p(0x100000 + 4096), None) == sg.SG_EALIAS
+    assert lib.sg_ca_steps(0, r, 64, 17, 16, a, b, ctypes.c_void_p(0x7000000000 + 65520), None) == sg.SG_EALIAS
+    assert lib.sg_ca_steps(0, r, 64, 17, 16, a, ctypes.c_void_p(0x100000 + 16), w, None) == sg.SG_EALIAS
+    # misaligned work buffer
+    assert lib.sg_ca_steps(0, r, 64, 20, 8, a, b, ctypes.c_void_p(0x7100000004), None) == sg.SG_EINVAL

@@ -185,6 +185,51 @@ def test_ca_full_size_sampled(r, rho):
         assert not got[y0:y1][~inputs.gasket_rows(n, y0, y1)].any()
 
 
+# ------------------------------------------------------------------ multi-step life
+
+def gpu_ca_steps(map_kind, r, rho, a0, steps, spp):
+    a = dev(a0)
+    out = torch.zeros_like(a)
+    work = torch.zeros_like(a)
+    sg.sg_ca_steps(map_kind, r, rho, steps, a, out, work, steps_per_pass=spp)
+    torch.cuda.synchronize()
+    assert torch.equal(a, dev(a0))  # the input is read only
+    return out
+
+
+@pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
+@pytest.mark.parametrize("r,rho,steps,spp", [
+    (6, 64, 1, 16), (6, 64, 16, 16), (7, 64, 23, 8), (7, 128, 5, 5), (8, 256, 40, 16),
+    (9, 64, 33, 16), (10, 128, 50, 16), (10, 256, 17, 16), (10, 64, 12, 1), (11, 128, 31, 7),
+    (8, 16, 9, 1), (9, 4, 3, 0), (10, 256, 0, 16), (12, 256, 100, 16), (12, 128, 100, 11)])
+def test_ca_steps_exact(map_kind, r, rho, steps, spp):
+    note(f"ca_steps {map_kind} r={r} rho={rho} steps={steps} per_pass={spp}")
+    a0 = inputs.bernoulli_state(r, 0.5, 1706 + 3 * r)
+    got = gpu_ca_steps(map_kind, r, rho, a0, steps, spp).cpu().numpy()
+    ref = a0 if steps == 0 else O.life_steps(r, a0, steps)
+    assert np.array_equal(got, ref)
+
+
+
+
+@pytest.mark.parametrize("r,rho", [(16, 256), (16, 128), (14, 64)])
+def test_ca_steps_full_size_sampled(r, rho):
+    steps = 100
+    note(f"ca_steps full-size r={r} rho={rho} {steps} steps, 16 per pass")
+    n = 1 << r
+    a0 = inputs.bernoulli_state(r, 0.5, 1706)
+    tb = gpu_ca_steps("lambda", r, rho, a0, steps, 16)
+    one = gpu_ca("lambda", r, rho, a0, steps)  # one launch per generation
+    assert torch.equal(tb, one)
+    del one
+    got = tb.cpu().numpy()
+    del tb
+    rng = np.random.default_rng(100 + r)
+    for (x0, y0) in _windows(n, rng, 4, 64, 16):
+        ref = O.life_window(r, a0, x0, y0, 64, 16, steps)
+        assert np.array_equal(got[y0:y0 + 16, x0:x0 + 64], ref), (x0, y0)
+
+
 # ------------------------------------------------------------------ diffusion
 
 @pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
