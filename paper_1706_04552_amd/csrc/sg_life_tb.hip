@@ -8,15 +8,19 @@
 //     left/right (T <= 16 cells) from HBM, skipping chunks with no gasket
 //     cell, and bit-pack each 16-byte chunk of 0/1 bytes into 16 bits of an
 //     LDS plane (one bit per cell, 32 cells per word).
-//  2. List, once, the plane words that hold a gasket cell (wavefront ballot +
-//     prefix count), with each word's gasket mask (bounding sub-box test
+//  2. List, once, the vertical segments (one 32-cell word column, kSegRows
+//     rows) that hold a gasket cell (wavefront ballot + prefix count), and
+//     the gasket pattern of every region row (bounding sub-box test
 //     x & y == 0 applied to 32 cells at once).
-//  3. T times: every listed word computes its next state from the 3 x 3
-//     words around it with a bit-sliced adder (counts of the 8 neighbours as
-//     bit planes) and the B3/S23 rule, masked to the gasket; planes ping-pong
-//     with a barrier between generations.  Cells outside the region are taken
-//     as dead; the wrong values this makes at the region's cut edges move
-//     inward one cell per generation and never reach the tile in T <= 16.
+//  3. T times: each listed segment walks down its rows keeping the
+//     horizontal 3-cell sums of the rows above, at and below in registers
+//     (bit-sliced: lsb and carry planes), so every row's sums are formed once
+//     and used for three output rows; the count of the 8 neighbours and the
+//     B3/S23 rule are evaluated on the bit planes and masked to the gasket.
+//     Planes ping-pong with a barrier between generations.  Cells outside the
+//     region are taken as dead; the wrong values this makes at the region's
+//     cut edges move inward one cell per generation and never reach the tile
+//     in T <= 16.
 //  4. Unpack the tile and store every 64-byte granule that holds a gasket
 //     cell in full.
 #include "sg_device.h"
@@ -26,7 +30,33 @@ namespace sg {
 
 namespace {
 
-constexpr int kTbThreads = 256;
+// Workgroup shape; the defaults are the measured best on MI355X and can be
+// overridden at build time.
+#ifndef SG_TB_THREADS
+#define SG_TB_THREADS 0  // 0: 512 threads for rho = 256, 256 otherwise
+#endif
+#ifndef SG_TB_SEG_ROWS
+#define SG_TB_SEG_ROWS 5
+#endif
+#ifndef SG_TB_LOAD_BATCH
+#define SG_TB_LOAD_BATCH 4
+#endif
+template <int RHO>
+constexpr int tb_threads() {
+  return SG_TB_THREADS > 0 ? SG_TB_THREADS : (RHO >= 256 ? 512 : 256);
+}
+constexpr int kSegRows = SG_TB_SEG_ROWS;      // rows per vertical segment of a generation
+constexpr int kLoadBatch = SG_TB_LOAD_BATCH;  // global loads in flight per thread
+
+// Plane pitch (words per plane row) for a region W words wide.  Threads that
+// run consecutive segments of one word column touch rows kSegRows apart; a
+// pitch P with kSegRows * P = 1 (mod 32) puts those words in consecutive LDS
+// banks (32 banks of 4 bytes), so a wave's reads are conflict free.
+constexpr int plane_pitch(int W) {
+  for (int p = W + 2; p < W + 2 + 32; ++p)
+    if ((kSegRows * p) % 32 == 1) return p;
+  return W + 2;  // no such pitch (even kSegRows): plain row-major
+}
 
 // 16 bytes holding 0/1 -> 16 bits (bit i = byte i).
 __device__ __forceinline__ uint32_t pack16(const uint4 v) {
@@ -53,45 +83,60 @@ __device__ __forceinline__ uint32_t word_pattern(uint32_t y) {
   return m;
 }
 
-// Next state of 32 cells.  a, b, c: the word in the rows above, at and below;
-// *L / *R: the words to their left / right.  Neighbour counts are summed as
-// bit planes: each row contributes (lsb, carry) of its 3 (or 2) cells, the
-// three lsbs add to bit0 + 2k, and the count is 2 or 3 iff exactly one of
-// (carry_a, carry_b, carry_c, k) is set.
-__device__ __forceinline__ uint32_t life_word(uint32_t a, uint32_t aL, uint32_t aR,
-                                              uint32_t b, uint32_t bL, uint32_t bR,
-                                              uint32_t c, uint32_t cL, uint32_t cR) {
-  const uint32_t aw = __builtin_amdgcn_alignbit(a, aL, 31);  // west neighbours
-  const uint32_t ae = __builtin_amdgcn_alignbit(aR, a, 1);   // east neighbours
-  const uint32_t bw = __builtin_amdgcn_alignbit(b, bL, 31);
-  const uint32_t be = __builtin_amdgcn_alignbit(bR, b, 1);
-  const uint32_t cw = __builtin_amdgcn_alignbit(c, cL, 31);
-  const uint32_t ce = __builtin_amdgcn_alignbit(cR, c, 1);
-  const uint32_t sa = aw ^ a ^ ae, ca = (aw & a) | (aw & ae) | (a & ae);
-  const uint32_t sb = bw ^ be, cb = bw & be;
-  const uint32_t sc = cw ^ c ^ ce, cc = (cw & c) | (cw & ce) | (c & ce);
-  const uint32_t bit0 = sa ^ sb ^ sc;
-  const uint32_t k = (sa & sb) | (sa & sc) | (sb & sc);
-  const uint32_t x3 = ca ^ cb ^ cc;
-  const uint32_t m3 = (ca & cb) | (ca & cc) | (cb & cc);
-  const uint32_t o3 = ca | cb | cc;
-  const uint32_t e3 = x3 & ~m3;                   // exactly one carry
-  const uint32_t eq1 = (e3 & ~k) | (~o3 & k);     // exactly one of four
-  return eq1 & (bit0 | b);
+// Horizontal sums of a row word with its west and east neighbours, as bit
+// planes: (s, c) with value s + 2c.  Three cells (west, centre, east) for the
+// rows above and below, two (west, east) for the row itself.
+struct RowSums {
+  uint32_t s3, c3;  // west + centre + east
+  uint32_t s2, c2;  // west + east
+  uint32_t self;    // the centre cells
+};
+
+__device__ __forceinline__ RowSums row_sums(uint32_t left, uint32_t mid, uint32_t right) {
+  const uint32_t w = __builtin_amdgcn_alignbit(mid, left, 31);  // bit i <- cell x-1
+  const uint32_t e = __builtin_amdgcn_alignbit(right, mid, 1);  // bit i <- cell x+1
+  RowSums h;
+  h.s3 = w ^ mid ^ e;
+  h.c3 = (w & mid) | (w & e) | (mid & e);
+  h.s2 = w ^ e;
+  h.c2 = w & e;
+  h.self = mid;
+  return h;
+}
+
+// B3/S23 for 32 cells from the sums of the rows above (u), at (m) and below
+// (d).  The neighbour count is bit0 + 2 * (u.c3 + m.c2 + d.c3 + k), where
+// bit0 and k are the sum and carry of the three lsb planes; it is 2 or 3 iff
+// exactly one of those four carries is set.
+__device__ __forceinline__ uint32_t life_rule(const RowSums &u, const RowSums &m,
+                                              const RowSums &d) {
+  const uint32_t bit0 = u.s3 ^ m.s2 ^ d.s3;
+  const uint32_t k = (u.s3 & m.s2) | (u.s3 & d.s3) | (m.s2 & d.s3);
+  const uint32_t x3 = u.c3 ^ m.c2 ^ d.c3;
+  const uint32_t m3 = (u.c3 & m.c2) | (u.c3 & d.c3) | (m.c2 & d.c3);
+  const uint32_t o3 = u.c3 | m.c2 | d.c3;
+  const uint32_t e3 = x3 & ~m3;                // exactly one of the three carries
+  const uint32_t eq1 = (e3 & ~k) | (~o3 & k);  // exactly one of the four
+  return eq1 & (bit0 | m.self);
 }
 
 template <int RHO, bool LAMBDA>
-__global__ __launch_bounds__(kTbThreads) void k_life_tb(const uint8_t *__restrict__ in,
+__global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__restrict__ in,
                                                         uint8_t *__restrict__ out, int r,
                                                         int rb, uint64_t tile_base,
                                                         uint64_t ntiles, int T) {
   extern __shared__ uint32_t lds[];
-  __shared__ uint32_t nitems;
-  constexpr int W = RHO / 32 + 2;   // region words per row
-  constexpr int PW = W + 2;         // plane pitch (zero guard word each side)
-  constexpr int CH = RHO / 16 + 2;  // loaded 16-byte chunks per region row
-  const int R = RHO + 2 * T;        // region rows
-  const int PR = R + 2;             // plane rows (zero guard row each side)
+  __shared__ uint32_t nseg;
+  constexpr int kTbThreads = tb_threads<RHO>();
+  constexpr int W = RHO / 32 + 2;     // region words per row
+  constexpr int PW = plane_pitch(W);  // plane pitch (at least one zero guard word each side)
+  constexpr int CH = RHO / 16 + 2;    // loaded 16-byte chunks per region row
+  constexpr int L = kSegRows;
+  static_assert(L <= 8, "row bits of a segment are kept in 8 bits");
+  const int R = RHO + 2 * T;          // region rows
+  const int NB = (R + L - 1) / L;     // segment blocks per word column
+  const int RP = NB * L;              // region rows rounded up to whole blocks
+  const int PR = RP + 2;              // plane rows (zero guard row above, below)
   const int tid = threadIdx.x;
 
   const uint64_t t = tile_base + blockIdx.x;
@@ -104,65 +149,106 @@ __global__ __launch_bounds__(kTbThreads) void k_life_tb(const uint8_t *__restric
     bx = (uint32_t)(t & ((1ull << rb) - 1ull));
     if ((bx & by) != 0u) return;
   }
-  const int64_t n = (int64_t)1 << r;
-  const int64_t X0 = (int64_t)bx * RHO, Y0 = (int64_t)by * RHO;
-  const int64_t yr0 = Y0 - T;  // row of region row 0
+  // n <= 2^20, so cell coordinates (halo included) fit in 32-bit ints
+  const int n = 1 << r;
+  const int X0 = (int)bx * RHO, Y0 = (int)by * RHO;
+  const int yr0 = Y0 - T;  // row of region row 0
 
   uint32_t *plane0 = lds;
   uint32_t *plane1 = lds + PR * PW;
-  uint32_t *items = plane1 + PR * PW;
-  uint32_t *imask = items + R * W;
+  uint32_t *rowpat = plane1 + PR * PW;  // RP: gasket pattern of each region row
+  uint32_t *segs = rowpat + RP;         // W * NB: listed segments
 
   for (int i = tid; i < 2 * PR * PW; i += kTbThreads) lds[i] = 0u;
-  if (tid == 0) nitems = 0u;
+  for (int i = tid; i < RP; i += kTbThreads) {
+    const int y = yr0 + i;
+    rowpat[i] = (i < R && y >= 0 && y < n) ? word_pattern((uint32_t)y) : 0u;
+  }
+  if (tid == 0) nseg = 0u;
   __syncthreads();
 
-  // 1. load and bit-pack the region
+  // 1. load and bit-pack the region, kLoadBatch loads in flight per thread
   uint16_t *p0h = reinterpret_cast<uint16_t *>(plane0);
-  for (int e = tid; e < R * CH; e += kTbThreads) {
-    const int i = e / CH, j = e - (e / CH) * CH;
-    const int64_t y = yr0 + i, x = X0 - 16 + 16 * j;
-    if (y < 0 || y >= n || x < 0 || x >= n || (x & y) != 0) continue;
-    const uint4 v = *reinterpret_cast<const uint4 *>(in + y * n + x);
-    const int w = (j + 1) >> 1, half = (j + 1) & 1;
-    p0h[((i + 1) * PW + (w + 1)) * 2 + half] = (uint16_t)pack16(v);
+  for (int e0 = 0; e0 < R * CH; e0 += kTbThreads * kLoadBatch) {
+    uint4 v[kLoadBatch];
+    int slot[kLoadBatch];
+#pragma unroll
+    for (int q = 0; q < kLoadBatch; ++q) {
+      const int e = e0 + q * kTbThreads + tid;
+      slot[q] = -1;
+      v[q] = make_uint4(0u, 0u, 0u, 0u);
+      if (e < R * CH) {
+        const int i = e / CH, j = e - (e / CH) * CH;
+        const int y = yr0 + i, x = X0 - 16 + 16 * j;
+        if (y >= 0 && y < n && x >= 0 && x < n && (x & y) == 0) {
+          v[q] = *reinterpret_cast<const uint4 *>(in + (size_t)y * n + x);
+          slot[q] = ((i + 1) * PW + (((j + 1) >> 1) + 1)) * 2 + ((j + 1) & 1);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kLoadBatch; ++q)
+      if (slot[q] >= 0) p0h[slot[q]] = (uint16_t)pack16(v[q]);
   }
 
-  // 2. compact list of the words that hold a gasket cell
+  // 2. compact list of the segments (word column w, rows [b*L, b*L+L)) that
+  //    hold a gasket cell, listed column by column; each entry keeps the
+  //    rows whose word starts on the gasket (x & y == 0 for its first cell)
   const int lane = __lane_id();
-  for (int base = 0; base < R * W; base += kTbThreads) {
+  for (int base = 0; base < W * NB; base += kTbThreads) {
     const int e = base + tid;
-    uint32_t m = 0u;
-    int idx = 0;
-    if (e < R * W) {
-      const int i = e / W, w = e - (e / W) * W;
-      const int64_t y = yr0 + i, xw = X0 - 32 + 32 * w;
-      if (y >= 0 && y < n && xw >= 0 && xw < n && (xw & y) == 0) m = word_pattern((uint32_t)y);
-      idx = (i + 1) * PW + (w + 1);
+    uint32_t rows = 0u, code = 0u;
+    if (e < W * NB) {
+      const int w = e / NB, b = e - (e / NB) * NB;
+      const int xw = X0 - 32 + 32 * w;
+      if (xw >= 0 && xw < n) {
+#pragma unroll
+        for (int q = 0; q < L; ++q) {
+          const int i = b * L + q;
+          if (rowpat[i] != 0u && (xw & (yr0 + i)) == 0) rows |= 1u << q;
+        }
+      }
+      code = (uint32_t)w | ((uint32_t)b << 8) | (rows << 24);
     }
-    const uint64_t ball = __ballot(m != 0u);
+    const uint64_t ball = __ballot(rows != 0u);
     const uint32_t before = (uint32_t)__popcll(ball & ((1ull << lane) - 1ull));
     uint32_t off = 0u;
-    if (lane == 0 && ball != 0ull) off = atomicAdd(&nitems, (uint32_t)__popcll(ball));
+    if (lane == 0 && ball != 0ull) off = atomicAdd(&nseg, (uint32_t)__popcll(ball));
     off = __shfl(off, 0);
-    if (m != 0u) {
-      items[off + before] = (uint32_t)idx;
-      imask[off + before] = m;
-    }
+    if (rows != 0u) segs[off + before] = code;
   }
   __syncthreads();
-  const int ni = (int)nitems;
+  const int ns = (int)nseg;
 
-  // 3. T generations in LDS
+  // 3. T generations in LDS, one vertical segment per thread at a time
   for (int s = 0; s < T; ++s) {
     const uint32_t *src = (s & 1) ? plane1 : plane0;
     uint32_t *dst = (s & 1) ? plane0 : plane1;
-    for (int e = tid; e < ni; e += kTbThreads) {
-      const int idx = (int)items[e];
-      const uint32_t *p = src + idx;
-      dst[idx] = life_word(p[-PW], p[-PW - 1], p[-PW + 1], p[0], p[-1], p[1], p[PW],
-                           p[PW - 1], p[PW + 1]) &
-                 imask[e];
+    for (int k = tid; k < ns; k += kTbThreads) {
+      const uint32_t code = segs[k];
+      const int w = (int)(code & 0xffu), i0 = (int)((code >> 8) & 0xffffu) * L;
+      const uint32_t rows = code >> 24;
+      const int idx0 = (i0 + 1) * PW + (w + 1);
+      // all rows the segment reads, before any store (the planes may alias as
+      // far as the compiler knows, so loads are not moved past stores)
+      uint32_t row[L + 2][3];
+#pragma unroll
+      for (int q = 0; q < L + 2; ++q) {
+        const uint32_t *p = src + idx0 + (q - 1) * PW;
+        row[q][0] = p[-1];
+        row[q][1] = p[0];
+        row[q][2] = p[1];
+      }
+      RowSums up = row_sums(row[0][0], row[0][1], row[0][2]);
+      RowSums mid = row_sums(row[1][0], row[1][1], row[1][2]);
+#pragma unroll
+      for (int q = 0; q < L; ++q) {
+        const RowSums dn = row_sums(row[q + 2][0], row[q + 2][1], row[q + 2][2]);
+        const uint32_t m = rowpat[i0 + q] & (0u - ((rows >> q) & 1u));
+        dst[idx0 + q * PW] = life_rule(up, mid, dn) & m;
+        up = mid;
+        mid = dn;
+      }
     }
     __syncthreads();
   }
@@ -172,18 +258,19 @@ __global__ __launch_bounds__(kTbThreads) void k_life_tb(const uint8_t *__restric
   constexpr int TC = RHO / 16;
   for (int e = tid; e < RHO * TC; e += kTbThreads) {
     const int ty = e / TC, j = e - (e / TC) * TC;
-    const int64_t y = Y0 + ty, x = X0 + 16 * j;
-    if (((x & ~(int64_t)63) & y) != 0) continue;
+    const int y = Y0 + ty, x = X0 + 16 * j;
+    if (((x & ~63) & y) != 0) continue;
     const int w = 1 + (j >> 1), half = j & 1;
     const uint32_t bits = fin[((T + ty + 1) * PW + (w + 1)) * 2 + half];
-    *reinterpret_cast<uint4 *>(out + y * n + x) = unpack16(bits);
+    *reinterpret_cast<uint4 *>(out + (size_t)y * n + x) = unpack16(bits);
   }
 }
 
 template <int RHO>
 size_t tb_lds_bytes(int T) {
-  const int W = RHO / 32 + 2, PW = W + 2, R = RHO + 2 * T, PR = R + 2;
-  return sizeof(uint32_t) * (size_t)(2 * PR * PW + 2 * R * W);
+  const int W = RHO / 32 + 2, PW = plane_pitch(W), R = RHO + 2 * T;
+  const int NB = (R + kSegRows - 1) / kSegRows, RP = NB * kSegRows, PR = RP + 2;
+  return sizeof(uint32_t) * (size_t)(2 * PR * PW + RP + W * NB);
 }
 
 template <int RHO>
@@ -193,10 +280,10 @@ hipError_t life_tb_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out
   for (uint64_t g0 = 0; g0 < a.ntiles; g0 += per_launch) {
     const uint64_t g = a.ntiles - g0 < per_launch ? a.ntiles - g0 : per_launch;
     if (a.lambda)
-      hipLaunchKernelGGL((k_life_tb<RHO, true>), dim3((unsigned)g), dim3(kTbThreads), lds,
+      hipLaunchKernelGGL((k_life_tb<RHO, true>), dim3((unsigned)g), dim3(tb_threads<RHO>()), lds,
                          a.stream, in, out, a.r, a.rb, g0, a.ntiles, T);
     else
-      hipLaunchKernelGGL((k_life_tb<RHO, false>), dim3((unsigned)g), dim3(kTbThreads), lds,
+      hipLaunchKernelGGL((k_life_tb<RHO, false>), dim3((unsigned)g), dim3(tb_threads<RHO>()), lds,
                          a.stream, in, out, a.r, a.rb, g0, a.ntiles, T);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
