@@ -123,9 +123,10 @@ def main():
     torch.cuda.synchronize()
 
     if args.copy_calibration:
+        # a plain streaming kernel of known traffic: reads 1 GiB, writes 1 GiB
         src = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
-        ms = time_region(torch, lambda: dst.copy_(src), 5, 1)
+        ms = time_region(torch, lambda: torch.bitwise_not(src, out=dst), 5, 1)
         log(f"copy calibration: 1 GiB in {ms * 1e3:.1f} us = {2 * (1 << 30) / (ms * 1e-3) / 1e9:.0f} GB/s")
         del src, dst
 
@@ -181,15 +182,20 @@ def main():
     wl = min(wp["lambda"], key=lambda k: wp["lambda"][k])
     wb = min(wp["bbox"], key=lambda k: wp["bbox"][k])
 
-    achieved = CA_BYTES_PER_CELL * cells / (best_ms * 1e-3) / 1e9
+    # roofline of the dominant kernel, per launch: the timed region runs
+    # `launches` launches of it back to back for args.steps generations
+    launches = -(-args.steps // best_T)
+    launch_bytes = CA_BYTES_PER_CELL * cells * args.steps / launches
+    launch_us = best_ms * args.steps / launches * 1e3
+    achieved = launch_bytes / (launch_us * 1e-6) / 1e9
     kname = (f"k_life_tb<{best_rho}, lambda>" if best_T > 1 else
              (f"k_life_strip<{best_rho}, lambda>" if best_rho >= 32 else f"k_life<{best_rho}, lambda>"))
-    traffic = traffic_from_profile(f"ca_r{R}_rho{best_rho}_T{best_T}")
+    traffic = traffic_from_profile(f"life_r{R}_rho{best_rho}_T{best_T}_steps{args.steps}")
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": traffic, "kernel": kname,
-                "algorithmic_bytes_per_launch": CA_BYTES_PER_CELL * cells * best_T,
-                "launch_duration_us": round(best_ms * best_T * 1e3, 2)}
+                "algorithmic_bytes_per_launch": round(launch_bytes),
+                "launch_duration_us": round(launch_us, 2), "launches": launches}
 
     cpu = None
     if not args.no_cpu_baseline:
