@@ -145,6 +145,98 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
 SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in,
                            float *d_out, float alpha, void *stream);
 
+/* ---------------------------------------------------------------------
+ * Many gaskets at once (a batch of independent embedded gaskets of uneven
+ * levels).  Every entry point below runs the temporally blocked life pass of
+ * sg_ca_steps over the lambda tiles of all gaskets in one persistent launch
+ * per pass; each gasket's result is identical to sg_ca_steps on it alone.
+ * --------------------------------------------------------------------- */
+
+/* Launch shape of a batched pass.
+ *   rho:            lambda tile side, 64, 128 or 256 (<= every gasket's n)
+ *   steps_per_pass: generations per pass, 1..16
+ *   groups_per_cu:  persistent workgroups per compute unit, 1..64, or 0 for
+ *                   one workgroup per tile
+ *   threads:        threads per workgroup, 256 or 512 */
+typedef struct sg_tune {
+    int32_t rho;
+    int32_t steps_per_pass;
+    int32_t groups_per_cu;
+    int32_t threads;
+} sg_tune;
+
+/* One gasket of a batch: `steps` generations from d_in into d_out, with
+ * d_work as the third buffer when more than one pass runs (as sg_ca_steps).
+ * All device pointers, n * n bytes, 16-byte aligned, 0 off the gasket. */
+typedef struct sg_gasket {
+    const uint8_t *in;
+    uint8_t *out;
+    uint8_t *work;
+    int32_t r;
+    int32_t steps;
+} sg_gasket;
+
+/* One gasket of a single batched pass: `steps` (0..steps_per_pass)
+ * generations from src into dst; items with steps = 0 are skipped. */
+typedef struct sg_pass_item {
+    const uint8_t *src;
+    uint8_t *dst;
+    int32_t r;
+    int32_t steps;
+} sg_pass_item;
+
+typedef struct sg_batch sg_batch;       /* planned batch with a captured hipGraph */
+typedef struct sg_pass_ctx sg_pass_ctx; /* device item table for repeated passes */
+
+/* Host only.  A valid default shape (rho 64, 16 generations per pass, one
+ * workgroup per tile, 256 threads). */
+SG_API int sg_tune_default(sg_tune *tune);
+
+/* Plans the passes of `count` gaskets (host array, copied), uploads the
+ * per-pass item tables to device memory owned by the handle, and captures
+ * all passes (and a device copy in -> out for gaskets with steps = 0) into a
+ * hipGraph.  Allocates; not for the hot path.  The gaskets' buffers must stay
+ * valid while the handle is used.
+ * Errors: SG_EINVAL (bad shape, r < log2 rho, missing work buffer),
+ * SG_EALIAS, SG_ENOMEM, SG_EHIP. */
+SG_API int sg_batch_create(const sg_gasket *gaskets, int count, const sg_tune *tune,
+                           sg_batch **out);
+
+/* Runs the whole batch: one hipGraphLaunch on `stream`. */
+SG_API int sg_batch_run(sg_batch *batch, void *stream);
+
+/* Runs the same launches as sg_batch_run without the graph. */
+SG_API int sg_batch_run_eager(sg_batch *batch, void *stream);
+
+/* Number of passes and of gasket cell updates (sum of 3^r * steps) of a run. */
+SG_API int sg_batch_stats(const sg_batch *batch, uint64_t *passes, uint64_t *cell_steps);
+
+/* Frees the handle, its graph and its device tables (NULL is ignored). */
+SG_API void sg_batch_destroy(sg_batch *batch);
+
+/* Times every candidate shape (rho in {64, 128, 256} not above the smallest
+ * gasket, 8 or 16 generations per pass, 0/2/4/8 groups per compute unit,
+ * 256/512 threads) by running the batch on `stream` (writes the gaskets'
+ * out/work buffers, never their inputs) and returns the fastest shape and
+ * its time.  Synchronises the stream.  Errors as sg_batch_create. */
+SG_API int sg_batch_autotune(const sg_gasket *gaskets, int count, sg_tune *best,
+                             float *best_ms, void *stream);
+
+/* Device item table for up to `capacity` gaskets per pass (continuous
+ * batching: the set of gaskets changes from pass to pass).  Allocates device
+ * and pinned host memory.  Errors: SG_EINVAL, SG_ENOMEM, SG_EHIP. */
+SG_API int sg_pass_ctx_create(int capacity, sg_pass_ctx **out);
+
+/* One batched pass over `count` items (host array, validated, then uploaded
+ * asynchronously on `stream`).  Successive calls on one context must use
+ * the same stream.  Errors: SG_EINVAL (count > capacity, steps outside
+ * 0..steps_per_pass, r < log2 rho), SG_EALIAS, SG_EHIP. */
+SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
+                       const sg_tune *tune, void *stream);
+
+/* Waits for the context's last upload and frees it (NULL is ignored). */
+SG_API void sg_pass_ctx_destroy(sg_pass_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,7 @@ input generators stay usable without a GPU runtime.
 """
 import importlib
 
-__all__ = ["sg", "inputs", "build"]
+__all__ = ["sg", "inputs", "build", "batch", "serving"]
 
 
 def __getattr__(name):

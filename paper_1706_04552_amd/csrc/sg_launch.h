@@ -29,4 +29,17 @@ constexpr int kMaxStepsPerPass = 16;
 bool life_tb_supported(int rho);
 hipError_t launch_life_tb(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
 
+// One pass over many gaskets (device table of items, sorted by tile_begin,
+// every item with at least one tile and 1 <= steps <= max_steps).
+struct BatchItem {
+  const uint8_t *src;   // state before the pass
+  uint8_t *dst;         // state after the pass
+  uint64_t tile_begin;  // global index of the item's first lambda tile
+  int32_t r;            // level: n = 2^r (r >= log2 rho)
+  int32_t steps;        // generations in this pass
+};
+hipError_t launch_life_tb_batch(int rho, int threads, const BatchItem *d_items, int count,
+                                uint64_t total_tiles, int max_steps, int groups,
+                                hipStream_t stream);
+
 }  // namespace sg

@@ -58,6 +58,8 @@ constexpr int plane_pitch(int W) {
   return W + 2;  // no such pitch (even kSegRows): plain row-major
 }
 
+constexpr int rho_log2_const(int rho) { return rho <= 1 ? 0 : 1 + rho_log2_const(rho / 2); }
+
 // 16 bytes holding 0/1 -> 16 bits (bit i = byte i).
 __device__ __forceinline__ uint32_t pack16(const uint4 v) {
   auto p4 = [](uint32_t w) { return (w | (w >> 7) | (w >> 14) | (w >> 21)) & 0xFu; };
@@ -120,14 +122,16 @@ __device__ __forceinline__ uint32_t life_rule(const RowSums &u, const RowSums &m
   return eq1 & (bit0 | m.self);
 }
 
-template <int RHO, bool LAMBDA>
-__global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__restrict__ in,
-                                                        uint8_t *__restrict__ out, int r,
-                                                        int rb, uint64_t tile_base,
-                                                        uint64_t ntiles, int T) {
-  extern __shared__ uint32_t lds[];
-  __shared__ uint32_t nseg;
-  constexpr int kTbThreads = tb_threads<RHO>();
+// One tile pass: the rho x rho tile at block (bx, by) of the gasket in `in`
+// (level r) advanced by T generations into `out`, by NT threads.  `lds` holds
+// tb_lds_bytes<RHO>(T) bytes (or more); the caller synchronises the workgroup
+// before reusing it.
+template <int RHO, int NT>
+__device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
+                                        uint8_t *__restrict__ out, int r, uint32_t bx,
+                                        uint32_t by, int T, uint32_t *lds, uint32_t *nseg_p) {
+  uint32_t &nseg = *nseg_p;
+  constexpr int kTbThreads = NT;
   constexpr int W = RHO / 32 + 2;     // region words per row
   constexpr int PW = plane_pitch(W);  // plane pitch (at least one zero guard word each side)
   constexpr int CH = RHO / 16 + 2;    // loaded 16-byte chunks per region row
@@ -139,16 +143,6 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__
   const int PR = RP + 2;              // plane rows (zero guard row above, below)
   const int tid = threadIdx.x;
 
-  const uint64_t t = tile_base + blockIdx.x;
-  if (t >= ntiles) return;
-  uint32_t bx, by;
-  if constexpr (LAMBDA) {
-    lambda_decode((uint32_t)t, rb, bx, by);
-  } else {
-    by = (uint32_t)(t >> rb);
-    bx = (uint32_t)(t & ((1ull << rb) - 1ull));
-    if ((bx & by) != 0u) return;
-  }
   // n <= 2^20, so cell coordinates (halo included) fit in 32-bit ints
   const int n = 1 << r;
   const int X0 = (int)bx * RHO, Y0 = (int)by * RHO;
@@ -266,6 +260,52 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__
   }
 }
 
+// One workgroup per tile of one gasket.
+template <int RHO, bool LAMBDA>
+__global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__restrict__ in,
+                                                               uint8_t *__restrict__ out, int r,
+                                                               int rb, uint64_t tile_base,
+                                                               uint64_t ntiles, int T) {
+  extern __shared__ uint32_t lds[];
+  __shared__ uint32_t nseg;
+  const uint64_t t = tile_base + blockIdx.x;
+  if (t >= ntiles) return;
+  uint32_t bx, by;
+  if constexpr (LAMBDA) {
+    lambda_decode((uint32_t)t, rb, bx, by);
+  } else {
+    by = (uint32_t)(t >> rb);
+    bx = (uint32_t)(t & ((1ull << rb) - 1ull));
+    if ((bx & by) != 0u) return;
+  }
+  tb_tile<RHO, tb_threads<RHO>()>(in, out, r, bx, by, T, lds, &nseg);
+}
+
+// Many gaskets in one persistent launch: workgroups stride over the global
+// tile index of all items (each item's lambda tiles numbered from its
+// tile_begin, items sorted by tile_begin), find the item by a binary search
+// (uniform per workgroup, so it runs on the scalar unit) and run the same
+// tile pass on that item's buffers with that item's generation count.
+template <int RHO, int NT>
+__global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restrict__ items,
+                                                      int count, uint64_t total_tiles) {
+  extern __shared__ uint32_t lds[];
+  __shared__ uint32_t nseg;
+  constexpr int K = rho_log2_const(RHO);
+  for (uint64_t g = blockIdx.x; g < total_tiles; g += gridDim.x) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].tile_begin <= g) lo = mid; else hi = mid - 1;
+    }
+    const BatchItem it = items[lo];
+    uint32_t bx, by;
+    lambda_decode((uint32_t)(g - it.tile_begin), it.r - K, bx, by);
+    tb_tile<RHO, NT>(it.src, it.dst, it.r, bx, by, it.steps, lds, &nseg);
+    __syncthreads();  // the next tile reuses the LDS planes
+  }
+}
+
 template <int RHO>
 size_t tb_lds_bytes(int T) {
   const int W = RHO / 32 + 2, PW = plane_pitch(W), R = RHO + 2 * T;
@@ -291,7 +331,35 @@ hipError_t life_tb_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out
   return hipSuccess;
 }
 
+template <int RHO, int NT>
+hipError_t life_tb_batch_rho(const BatchItem *d_items, int count, uint64_t total_tiles,
+                             int max_steps, int groups, hipStream_t stream) {
+  const size_t lds = tb_lds_bytes<RHO>(max_steps);
+  const uint64_t g = total_tiles < (uint64_t)groups ? total_tiles : (uint64_t)groups;
+  if (g == 0) return hipSuccess;
+  hipLaunchKernelGGL((k_life_tb_batch<RHO, NT>), dim3((unsigned)g), dim3(NT), lds, stream,
+                     d_items, count, total_tiles);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_life_tb_batch(int rho, int threads, const BatchItem *d_items, int count,
+                                uint64_t total_tiles, int max_steps, int groups,
+                                hipStream_t stream) {
+  if (max_steps < 1 || max_steps > kMaxStepsPerPass || groups < 1) return hipErrorInvalidValue;
+  const bool t512 = threads == 512;
+  if (threads != 256 && threads != 512) return hipErrorInvalidValue;
+  switch (rho) {
+    case 64: return t512 ? life_tb_batch_rho<64, 512>(d_items, count, total_tiles, max_steps, groups, stream)
+                         : life_tb_batch_rho<64, 256>(d_items, count, total_tiles, max_steps, groups, stream);
+    case 128: return t512 ? life_tb_batch_rho<128, 512>(d_items, count, total_tiles, max_steps, groups, stream)
+                          : life_tb_batch_rho<128, 256>(d_items, count, total_tiles, max_steps, groups, stream);
+    case 256: return t512 ? life_tb_batch_rho<256, 512>(d_items, count, total_tiles, max_steps, groups, stream)
+                          : life_tb_batch_rho<256, 256>(d_items, count, total_tiles, max_steps, groups, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 bool life_tb_supported(int rho) { return rho == 64 || rho == 128 || rho == 256; }
 

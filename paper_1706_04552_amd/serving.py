@@ -1,0 +1,210 @@
+"""Continuous batching of gasket life solves on one GPU.
+
+Requests (a gasket level r, an initial state and a number of generations)
+arrive over time.  The scheduler admits them first-come first-served while
+their HBM footprint (two n x n uint8 buffers) fits under a cap, keeps their
+state resident on the device, and in every iteration advances every admitted
+request by up to `steps_per_pass` generations in ONE batched pass over the
+lambda tiles of all of them.  A request that finishes is retired and its
+memory released, so requests that arrived meanwhile join at the next
+iteration: their work overlaps on the device with the requests already
+running.
+
+The scheduler only orders work; the executor owns the buffers and runs the
+passes.  ``GpuExecutor`` runs them through libsg's batched pass; tests drive
+the same scheduler with a CPU executor.
+"""
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the start of serving
+    r: int                  # level: n = 2^r
+    steps: int              # life generations to run
+    state: Optional[np.ndarray] = None   # uint8 n x n initial state (host)
+    template: Optional[int] = None       # or: the level of a device-resident template state
+
+
+@dataclass
+class Result:
+    rid: int
+    r: int
+    steps: int
+    arrival: float
+    admitted: float
+    finished: float
+    output: Optional[np.ndarray] = None
+    rejected: bool = False
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def footprint(r: int) -> int:
+    """HBM bytes a request holds while resident: two n x n uint8 buffers."""
+    return 2 * (1 << r) * (1 << r)
+
+
+@dataclass
+class _Slot:
+    req: Request
+    handle: object
+    remaining: int
+    admitted: float
+
+
+@dataclass
+class ServeStats:
+    results: List[Result] = field(default_factory=list)
+    makespan: float = 0.0
+    iterations: int = 0
+    max_resident_bytes: int = 0
+    max_active: int = 0
+
+    def summary(self) -> Dict[str, float]:
+        done = [x for x in self.results if not x.rejected]
+        lat = np.array([x.latency for x in done]) if done else np.zeros(1)
+        cells = float(sum((3 ** x.r) * x.steps for x in done))
+        return {"requests": len(done), "rejected": len(self.results) - len(done),
+                "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3),
+                "makespan_s": self.makespan, "cells_per_s": cells / max(self.makespan, 1e-12),
+                "iterations": self.iterations, "max_active": self.max_active,
+                "max_resident_gb": self.max_resident_bytes / 1e9}
+
+
+class ContinuousBatcher:
+    """FIFO admission by HBM footprint, one batched pass per iteration."""
+
+    def __init__(self, executor, cap_bytes: int, steps_per_pass: int,
+                 keep_outputs: bool = False, clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep):
+        self.ex = executor
+        self.cap = cap_bytes
+        self.T = steps_per_pass
+        self.keep_outputs = keep_outputs
+        self.clock = clock
+        self.sleep = sleep
+
+    def serve(self, requests: Sequence[Request]) -> ServeStats:
+        """Serve `requests` (arrival times in seconds after the start)."""
+        pending = sorted(requests, key=lambda q: (q.arrival, q.rid))
+        queue: List[Request] = []
+        active: List[_Slot] = []
+        used = 0
+        st = ServeStats()
+        t0 = self.clock()
+        now = 0.0
+        i = 0
+        while i < len(pending) or queue or active:
+            now = self.clock() - t0
+            while i < len(pending) and pending[i].arrival <= now:
+                queue.append(pending[i])
+                i += 1
+            # admission: first come first served while the footprint fits
+            while queue:
+                q = queue[0]
+                fp = footprint(q.r)
+                if fp > self.cap:  # can never fit
+                    queue.pop(0)
+                    st.results.append(Result(q.rid, q.r, q.steps, q.arrival, now, now, rejected=True))
+                    continue
+                if used + fp > self.cap:
+                    break
+                queue.pop(0)
+                h = self.ex.admit(q)
+                used += fp
+                active.append(_Slot(q, h, q.steps, now))
+            st.max_resident_bytes = max(st.max_resident_bytes, used)
+            st.max_active = max(st.max_active, len(active))
+            if not active:
+                if i < len(pending):  # idle until the next arrival
+                    wait = pending[i].arrival - (self.clock() - t0)
+                    if wait > 0:
+                        self.sleep(min(wait, 0.001))
+                continue
+            # one batched pass over every resident request
+            work = [(s.handle, min(self.T, s.remaining)) for s in active]
+            self.ex.run_pass(work)
+            self.ex.sync()
+            st.iterations += 1
+            now = self.clock() - t0
+            still = []
+            for s, (_, k) in zip(active, work):
+                s.remaining -= k
+                if s.remaining > 0:
+                    still.append(s)
+                    continue
+                out = self.ex.download(s.handle) if self.keep_outputs else None
+                self.ex.release(s.handle)
+                used -= footprint(s.req.r)
+                st.results.append(Result(s.req.rid, s.req.r, s.req.steps, s.req.arrival,
+                                         s.admitted, now, out))
+            active = still
+        st.makespan = self.clock() - t0
+        return st
+
+
+class GpuExecutor:
+    """Device-resident states and libsg's batched pass (one launch per
+    iteration over all resident requests)."""
+
+    def __init__(self, tune, capacity: int = 4096, templates: Optional[Dict[int, object]] = None):
+        import torch
+        from .batch import PassContext
+        self.torch = torch
+        self.tune = tune
+        self.ctx = PassContext(capacity)
+        self.templates = templates or {}
+
+    def admit(self, q: Request):
+        torch = self.torch
+        n = 1 << q.r
+        if q.template is not None:
+            cur = self.templates[q.template].clone()
+        else:
+            cur = torch.from_numpy(np.ascontiguousarray(q.state)).cuda()
+        nxt = torch.zeros((n, n), dtype=torch.uint8, device=cur.device)
+        return {"r": q.r, "buf": [cur, nxt]}
+
+    def run_pass(self, work):
+        items = []
+        for h, k in work:
+            items.append((h["buf"][0], h["buf"][1], h["r"], k))
+        self.ctx.run(items, self.tune)
+        for h, k in work:
+            if k > 0:
+                h["buf"].reverse()
+
+    def sync(self):
+        self.torch.cuda.synchronize()
+
+    def download(self, h):
+        return h["buf"][0].cpu().numpy()
+
+    def release(self, h):
+        h["buf"] = None
+
+    def close(self):
+        self.ctx.close()
+
+
+def sequential_baseline(service_times: Sequence[float], arrivals: Sequence[float]):
+    """Latencies of a single-server FIFO queue that runs one request at a time
+    with the given measured service times (same arrivals, same order)."""
+    order = np.argsort(np.asarray(arrivals), kind="stable")
+    finish = 0.0
+    lat = np.zeros(len(arrivals))
+    for j in order:
+        start = max(arrivals[j], finish)
+        finish = start + service_times[j]
+        lat[j] = finish - arrivals[j]
+    return lat, finish

@@ -19,8 +19,28 @@ SG_MAP_LAMBDA, SG_MAP_BBOX = 0, 1
 SG_MAX_R, SG_MAX_RHO = 20, 256
 MAPS = {"lambda": SG_MAP_LAMBDA, "bbox": SG_MAP_BBOX}
 
+class sg_tune(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_int32), ("steps_per_pass", ctypes.c_int32),
+                ("groups_per_cu", ctypes.c_int32), ("threads", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class sg_gasket(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_void_p), ("out", ctypes.c_void_p), ("work", ctypes.c_void_p),
+                ("r", ctypes.c_int32), ("steps", ctypes.c_int32)]
+
+
+class sg_pass_item(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+                ("r", ctypes.c_int32), ("steps", ctypes.c_int32)]
+
+
 # Every symbol declared in include/sg.h, with its ctypes signature.
 _u64p = ctypes.POINTER(ctypes.c_uint64)
+_vp = ctypes.c_void_p
+_tunep = ctypes.POINTER(sg_tune)
 _SIGNATURES = {
     "sg_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sg_last_hip_error": (ctypes.c_char_p, []),
@@ -38,6 +58,18 @@ _SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "sg_diffuse_step": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
+    "sg_tune_default": (ctypes.c_int, [_tunep]),
+    "sg_batch_create": (ctypes.c_int, [ctypes.POINTER(sg_gasket), ctypes.c_int, _tunep,
+                                       ctypes.POINTER(_vp)]),
+    "sg_batch_run": (ctypes.c_int, [_vp, _vp]),
+    "sg_batch_run_eager": (ctypes.c_int, [_vp, _vp]),
+    "sg_batch_stats": (ctypes.c_int, [_vp, _u64p, _u64p]),
+    "sg_batch_destroy": (None, [_vp]),
+    "sg_batch_autotune": (ctypes.c_int, [ctypes.POINTER(sg_gasket), ctypes.c_int, _tunep,
+                                         ctypes.POINTER(ctypes.c_float), _vp]),
+    "sg_pass_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
+    "sg_pass_run": (ctypes.c_int, [_vp, ctypes.POINTER(sg_pass_item), ctypes.c_int, _tunep, _vp]),
+    "sg_pass_ctx_destroy": (None, [_vp]),
 }
 
 

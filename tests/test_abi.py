@@ -149,3 +149,44 @@ def test_ca_steps_validation(lib):
     assert lib.sg_ca_steps(0, r, 64, 17, 16, a, ctypes.c_void_p(0x100000 + 16), w, None) == sg.SG_EALIAS
     # misaligned work buffer
     assert lib.sg_ca_steps(0, r, 64, 20, 8, a, b, ctypes.c_void_p(0x7100000004), None) == sg.SG_EINVAL
+
+
+def test_batch_api_validation_on_the_host(lib):
+    from paper_1706_04552_amd import sg
+    t = sg.sg_tune()
+    assert lib.sg_tune_default(ctypes.byref(t)) == sg.SG_OK
+    assert (t.rho, t.steps_per_pass, t.threads) == (64, 16, 256)
+    assert lib.sg_tune_default(None) == sg.SG_EINVAL
+    h = ctypes.c_void_p()
+    a, b, w = 0x100000, 0x7000000000, 0x7100000000
+
+    def gaskets(*specs):
+        arr = (sg.sg_gasket * len(specs))()
+        for i, (r, steps, work) in enumerate(specs):
+            arr[i].in_, arr[i].out, arr[i].work = a + i * (1 << 21), b + i * (1 << 21), work
+            arr[i].r, arr[i].steps = r, steps
+        return arr
+
+    good = sg.sg_tune(64, 16, 0, 256)
+    for bad in [sg.sg_tune(32, 16, 0, 256), sg.sg_tune(64, 17, 0, 256), sg.sg_tune(64, 0, 0, 256),
+                sg.sg_tune(64, 16, -1, 256), sg.sg_tune(64, 16, 65, 256), sg.sg_tune(64, 16, 0, 128)]:
+        assert lib.sg_batch_create(gaskets((8, 10, w)), 1, ctypes.byref(bad), ctypes.byref(h)) == sg.SG_EINVAL
+    # gasket smaller than the tile, negative steps, missing work buffer, aliasing
+    assert lib.sg_batch_create(gaskets((5, 3, w)), 1, ctypes.byref(good), ctypes.byref(h)) == sg.SG_EINVAL
+    assert lib.sg_batch_create(gaskets((8, -1, w)), 1, ctypes.byref(good), ctypes.byref(h)) == sg.SG_EINVAL
+    assert lib.sg_batch_create(gaskets((8, 17, None)), 1, ctypes.byref(good), ctypes.byref(h)) == sg.SG_EINVAL
+    assert lib.sg_batch_create(gaskets((8, 17, a + 64)), 1, ctypes.byref(good), ctypes.byref(h)) == sg.SG_EALIAS
+    assert lib.sg_batch_create(gaskets((8, 3, w)), 0, ctypes.byref(good), ctypes.byref(h)) == sg.SG_EINVAL
+    assert lib.sg_batch_create(None, 2, ctypes.byref(good), ctypes.byref(h)) == sg.SG_EINVAL
+    assert lib.sg_batch_create(gaskets((8, 3, w)), 1, ctypes.byref(good), None) == sg.SG_EINVAL
+    assert not h.value
+    assert lib.sg_batch_run(None, None) == sg.SG_EINVAL
+    assert lib.sg_batch_run_eager(None, None) == sg.SG_EINVAL
+    assert lib.sg_batch_stats(None, None, None) == sg.SG_EINVAL
+    lib.sg_batch_destroy(None)
+    assert lib.sg_batch_autotune(gaskets((8, 3, w)), 1, None, None, None) == sg.SG_EINVAL
+    assert lib.sg_pass_ctx_create(0, ctypes.byref(h)) == sg.SG_EINVAL
+    assert lib.sg_pass_ctx_create(4, None) == sg.SG_EINVAL
+    item = (sg.sg_pass_item * 1)()
+    assert lib.sg_pass_run(None, item, 1, ctypes.byref(good), None) == sg.SG_EINVAL
+    lib.sg_pass_ctx_destroy(None)

@@ -1,0 +1,159 @@
+"""GPU parity of the batched paths: many gaskets of uneven levels in one
+persistent launch per pass (graph-captured or eager), the per-iteration pass
+of continuous batching, the autotuner's choice, and the serving loop.  Each
+gasket's result must be bit-exact with the oracle and identical to the same
+gasket run alone through sg_ca_steps."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1706_04552_amd import batch as B
+from paper_1706_04552_amd import inputs, sg
+from paper_1706_04552_amd.serving import ContinuousBatcher, GpuExecutor, Request, footprint
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[case] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    sg.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def make_gaskets(count, r_lo, r_hi, steps_lo, steps_hi, seed):
+    rng = np.random.default_rng(seed)
+    hosts, gs = [], []
+    for i in range(count):
+        r = int(rng.integers(r_lo, r_hi + 1))
+        steps = int(rng.integers(steps_lo, steps_hi + 1))
+        p = float(rng.uniform(0.2, 0.8))
+        a0 = inputs.bernoulli_state(r, p, seed * 1000 + i)
+        inp = torch.from_numpy(a0).cuda()
+        gs.append(B.Gasket(r, steps, inp, torch.zeros_like(inp), torch.zeros_like(inp)))
+        hosts.append(a0)
+    return hosts, gs
+
+
+def oracle_check(r, a0, steps, got):
+    if r <= 9:
+        assert np.array_equal(got, O.life_steps(r, a0, steps) if steps else a0)
+    else:
+        n = 1 << r
+        for (x0, y0) in [(0, 0), (n - 48, 0), (0, n - 8), (n // 3, n // 5)]:
+            ref = O.life_window(r, a0, x0, y0, 48, 8, steps)
+            assert np.array_equal(got[y0:y0 + 8, x0:x0 + 48], ref), (r, x0, y0)
+
+
+def solo(g, T=16):
+    out = torch.zeros_like(g.inp)
+    work = torch.zeros_like(g.inp)
+    sg.sg_ca_steps("lambda", g.r, 64, g.steps, g.inp, out, work, steps_per_pass=T)
+    return out
+
+
+def test_batch_graph_replays_equal_eager_solo_and_oracle():
+    note("batch of 48 gaskets r=6..11, steps 0..40, graph and eager")
+    hosts, gs = make_gaskets(48, 6, 11, 0, 40, 3)
+    tune = B.make_tune(rho=64, steps_per_pass=16, groups_per_cu=2, threads=256)
+    with B.Batch(gs, tune) as bt:
+        st = bt.stats()
+        assert st["passes"] == max(-(-g.steps // 16) for g in gs)
+        assert st["cell_steps"] == sum(3 ** g.r * g.steps for g in gs)
+        bt.run(graph=False)
+        torch.cuda.synchronize()
+        eager = [g.out.clone() for g in gs]
+        for rep in range(3):
+            for g in gs:
+                g.out.zero_()
+                g.work.zero_()
+            torch.cuda.synchronize()
+            bt.run(graph=True)
+            torch.cuda.synchronize()
+            for g, e in zip(gs, eager):
+                assert torch.equal(g.out, e), rep
+    for g, e, a0 in zip(gs, eager, hosts):
+        assert torch.equal(e, solo(g))
+        oracle_check(g.r, a0, g.steps, e.cpu().numpy())
+
+
+@pytest.mark.parametrize("rho,spp,gpc,threads", [(64, 8, 0, 512), (128, 16, 4, 256),
+                                                 (128, 5, 1, 512), (256, 16, 8, 256)])
+def test_batch_launch_shapes_agree(rho, spp, gpc, threads):
+    note(f"batch shapes rho={rho} per_pass={spp} groups_per_cu={gpc} threads={threads}")
+    hosts, gs = make_gaskets(24, 8, 11, 1, 35, 11)
+    ref = [solo(g) for g in gs]
+    with B.Batch(gs, B.make_tune(rho, spp, gpc, threads)) as bt:
+        bt.run(graph=True)
+        torch.cuda.synchronize()
+    for g, e in zip(gs, ref):
+        assert torch.equal(g.out, e)
+    oracle_check(gs[0].r, hosts[0], gs[0].steps, gs[0].out.cpu().numpy())
+
+
+def test_autotune_returns_a_valid_shape():
+    note("autotune on 16 gaskets r=7..10")
+    hosts, gs = make_gaskets(16, 7, 10, 5, 30, 5)
+    tune, ms = B.autotune(gs)
+    assert ms > 0 and tune.rho in (64, 128) and tune.threads in (256, 512)
+    assert 1 <= tune.steps_per_pass <= 16 and tune.groups_per_cu in (0, 2, 4, 8)
+    for g in gs:
+        g.out.zero_()
+        g.work.zero_()
+    with B.Batch(gs, tune) as bt:
+        bt.run()
+        torch.cuda.synchronize()
+    for g, a0 in zip(gs, hosts):
+        oracle_check(g.r, a0, g.steps, g.out.cpu().numpy())
+
+
+def test_pass_context_mixed_steps():
+    note("pass context: one pass over gaskets with different generation counts")
+    hosts, gs = make_gaskets(20, 6, 10, 0, 12, 9)
+    ctx = B.PassContext(64)
+    tune = B.make_tune(64, 12, 2, 256)
+    items = [(g.inp, g.out, g.r, g.steps) for g in gs]
+    ctx.run(items, tune)
+    torch.cuda.synchronize()
+    for g, a0 in zip(gs, hosts):
+        if g.steps:
+            oracle_check(g.r, a0, g.steps, g.out.cpu().numpy())
+    # a second pass on the same context (staging reuse) continues from out
+    ctx.run([(g.out, g.work, g.r, 3) for g in gs], tune)
+    torch.cuda.synchronize()
+    for g, a0 in zip(gs[:6], hosts[:6]):
+        if g.steps:
+            oracle_check(g.r, a0, g.steps + 3, g.work.cpu().numpy())
+    ctx.close()
+
+
+def test_serving_results_equal_alone_and_respect_the_cap():
+    note("continuous batching: 40 requests r=6..10")
+    rng = np.random.default_rng(21)
+    reqs = []
+    for i in range(40):
+        r = int(rng.integers(6, 11))
+        steps = int(rng.integers(0, 60))
+        reqs.append(Request(i, float(rng.uniform(0, 0.02)), r, steps,
+                            inputs.bernoulli_state(r, 0.5, 500 + i)))
+    cap = 6 * footprint(10)
+    ex = GpuExecutor(B.make_tune(64, 8, 2, 256), capacity=64)
+    st = ContinuousBatcher(ex, cap_bytes=cap, steps_per_pass=8, keep_outputs=True).serve(reqs)
+    ex.close()
+    assert st.max_resident_bytes <= cap and st.max_active >= 2
+    assert len(st.results) == 40 and not any(x.rejected for x in st.results)
+    for res in st.results:
+        q = reqs[res.rid]
+        inp = torch.from_numpy(q.state).cuda()
+        g = B.Gasket(q.r, q.steps, inp, torch.zeros_like(inp), torch.zeros_like(inp))
+        alone = solo(g, T=8).cpu().numpy()
+        assert np.array_equal(res.output, alone), res.rid
+        oracle_check(q.r, q.state, q.steps, res.output)
