@@ -89,6 +89,199 @@ def cpu_baseline(r, a0_host, min_seconds=10.0, max_gens=100):
                       f"benchmark's initial state, dense C oracle, {dt:.1f} s wall"}
 
 
+def graph_time(torch, launch, steps, reps=5):
+    """ms per step of `steps` launches captured in one hipGraph (the graph's
+    replay time; no host launch overhead), best of `reps` replays."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up outside the capture
+        for _ in range(2):
+            launch()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(steps):
+            launch()
+    g.replay()
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        best = ms if best is None else min(best, ms)
+    del g
+    return best
+
+
+def bench_sweep(torch, sg, inputs, rs, rhos, steps):
+    """Life steps (one launch per generation) at smaller sizes: lambda against
+    the bounding box at every rho, both timed as hipGraph replays."""
+    out = {}
+    for r in rs:
+        a0 = inputs.bernoulli_state(r, 0.5, SEED)
+        A = torch.from_numpy(a0).cuda()
+        Bf = torch.zeros_like(A)
+        row = {}
+        for rho in rhos:
+            t = {}
+            for map_kind in ("lambda", "bbox"):
+                bufs = [A.clone(), Bf.clone()]
+                st = {"i": 0}
+
+                def launch():
+                    i = st["i"]
+                    sg.sg_ca_step(map_kind, r, rho, bufs[i], bufs[1 - i])
+                    st["i"] = 1 - i
+                t[map_kind] = graph_time(torch, launch, steps)
+            row[str(rho)] = {"lambda_us": round(t["lambda"] * 1e3, 3),
+                             "bbox_us": round(t["bbox"] * 1e3, 3),
+                             "speedup": round(t["bbox"] / t["lambda"], 3)}
+            log(f"sweep r={r} rho={rho:3d}: lambda {t['lambda'] * 1e3:8.2f} us  bbox "
+                f"{t['bbox'] * 1e3:8.2f} us  x{t['bbox'] / t['lambda']:.2f}")
+        out[str(r)] = row
+        del A, Bf
+    return out
+
+
+def bench_diffusion(torch, sg, inputs, rhos, steps, warmup):
+    """FP32 diffusion at r = 14 (the diffusion workload's size), one launch per
+    step, lambda and bounding box at each rho; 8 algorithmic bytes per cell."""
+    r = 14
+    cells = 3 ** r
+    u0 = inputs.uniform_field(r, SEED)
+    U = torch.from_numpy(u0).cuda()
+    V = torch.zeros_like(U)
+    res = {"lambda": {}, "bbox": {}}
+    for map_kind in ("lambda", "bbox"):
+        for rho in rhos:
+            bufs = [U.clone(), V]
+            st = {"i": 0}
+
+            def step():
+                i = st["i"]
+                sg.sg_diffuse_step(map_kind, r, rho, bufs[i], bufs[1 - i], 0.2)
+                st["i"] = 1 - i
+            ms = time_region(torch, step, steps, warmup)
+            res[map_kind][rho] = ms
+            log(f"diffuse r=14 {map_kind:6s} rho={rho:3d}: {ms * 1e3:8.2f} us/step")
+            del bufs
+    # temporally blocked: 8 steps per pass at rho = 64, over `steps` steps
+    tb = {}
+    Out, Work = torch.zeros_like(U), torch.zeros_like(U)
+    for map_kind in ("lambda", "bbox"):
+        def run():
+            sg.sg_diffuse_steps(map_kind, r, 64, steps, U, Out, Work, 0.2, steps_per_pass=8)
+        tb[map_kind] = time_region(torch, run, 1, 1) / steps
+        log(f"diffuse r=14 {map_kind:6s} rho= 64 8/pass: {tb[map_kind] * 1e3:8.2f} us/step")
+    cands = [((rho, 1), ms) for rho, ms in res["lambda"].items()] + [((64, 8), tb["lambda"])]
+    (best, best_T), ms = min(cands, key=lambda kv: kv[1])
+    return {"r": r, "cells": cells,
+            "one_launch_per_step_us": {m: {str(k): round(v * 1e3, 2) for k, v in res[m].items()}
+                                       for m in res},
+            "rho64_8_per_pass_us": {m: round(v * 1e3, 2) for m, v in tb.items()},
+            "best": {"rho": best, "steps_per_launch": best_T}, "cells_per_s": cells / (ms * 1e-3),
+            "hbm_frac_algorithmic": round(8 * cells / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+
+
+def bench_batched(torch, sg, inputs, count, steps, runs):
+    """Many gaskets of uneven level (r ~ U{6..13}, Bernoulli(p), p ~ U[0.2, 0.8])
+    advanced `steps` generations: autotuned persistent batched passes in one
+    hipGraph, against the same launches without the graph and against one
+    gasket at a time."""
+    from paper_1706_04552_amd import batch
+    specs = inputs.batch_specs(count)
+    gs = []
+    for spec in specs:
+        inp = torch.from_numpy(spec.state()).cuda()
+        gs.append(batch.Gasket(spec.r, steps, inp, torch.zeros_like(inp), torch.zeros_like(inp)))
+    cell_steps = sum(3 ** g.r * steps for g in gs)
+    tune, tune_ms = batch.autotune(gs)
+    log(f"batched: autotuned {tune.as_dict()} ({tune_ms:.2f} ms)")
+    out = {"gaskets": count, "steps": steps, "cell_steps": cell_steps, "tune": tune.as_dict()}
+    with batch.Batch(gs, tune) as bt:
+        for name, graph in (("graph", True), ("eager", False)):
+            ms = time_region(torch, lambda: bt.run(graph=graph), runs, 1)
+            out[f"{name}_ms"] = round(ms, 3)
+            out[f"{name}_cells_per_s"] = cell_steps / (ms * 1e-3)
+            log(f"batched {name}: {ms:.3f} ms per run, {cell_steps / (ms * 1e-3) / 1e9:.1f} Gcells/s")
+        got = [g.out.clone() for g in gs[:8]]
+
+    def one_at_a_time():
+        for g in gs:
+            sg.sg_ca_steps("lambda", g.r, 64, steps, g.inp, g.out, g.work, steps_per_pass=16)
+    ms = time_region(torch, one_at_a_time, 1, 1)
+    out["one_at_a_time_ms"] = round(ms, 3)
+    out["one_at_a_time_cells_per_s"] = cell_steps / (ms * 1e-3)
+    log(f"batched one-at-a-time: {ms:.3f} ms")
+    out["same_as_alone"] = all(torch.equal(a, g.out) for a, g in zip(got, gs[:8]))
+    return out
+
+
+def bench_serving(torch, sg, inputs, qps_list, count, cap_gb):
+    """Poisson arrivals of life solves (r ~ U{8..15}, steps ~ U{10..200}) served
+    by continuous batching under an HBM footprint cap, against one request at
+    a time on the same arrivals (FIFO, each request's measured service time
+    alone, including the copy of its initial state into device buffers).
+    Requests of one level share an initial state (Bernoulli(0.5), seed
+    1706 + r); the passes' cost does not depend on it."""
+    from paper_1706_04552_amd import batch, serving
+    templates = {r: torch.from_numpy(inputs.bernoulli_state(r, 0.5, SEED + r)).cuda()
+                 for r in range(8, 16)}
+    # launch shape: autotuned once on a sample of the request mix
+    sample = inputs.poisson_requests(1.0, 48, seed=SEED + 7)
+    gs = [batch.Gasket(q.r, q.steps, templates[q.r], torch.zeros_like(templates[q.r]),
+                       torch.zeros_like(templates[q.r])) for q in sample]
+    tune, _ = batch.autotune(gs)
+    del gs
+    torch.cuda.empty_cache()
+    results = []
+    for qps in qps_list:
+        reqs = inputs.poisson_requests(qps, count)
+        rq = [serving.Request(q.rid, q.arrival, q.r, q.steps, template=q.r) for q in reqs]
+        ex = serving.GpuExecutor(tune, capacity=count, templates=templates)
+        server = serving.ContinuousBatcher(ex, cap_bytes=int(cap_gb * 1e9),
+                                           steps_per_pass=tune.steps_per_pass)
+        server.serve(rq[:16])  # warm-up (fills the buffer pool a little)
+        stats = server.serve(rq)
+        summ = stats.summary()
+        # one request at a time: each request alone (state copy + its steps)
+        svc = []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for q in rq:
+            h = ex.admit(q)  # pooled buffers, as the server uses
+            work = ex._buffer(q.r)
+            torch.cuda.synchronize()
+            e0.record()
+            h["buf"][0].copy_(templates[q.r])
+            sg.sg_ca_steps("lambda", q.r, tune.rho, q.steps, templates[q.r], h["buf"][1], work,
+                           steps_per_pass=tune.steps_per_pass)
+            e1.record()
+            torch.cuda.synchronize()
+            svc.append(e0.elapsed_time(e1) * 1e-3)
+            ex.release(h)
+            ex.pool[q.r].append(work)
+        ex.close()
+        lat, end = serving.sequential_baseline(svc, [q.arrival for q in rq])
+        cells = float(sum(3 ** q.r * q.steps for q in rq))
+        summ["one_at_a_time"] = {"p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                 "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                                 "cells_per_s": cells / end, "gpu_busy_s": float(sum(svc))}
+        summ.update({"qps": qps, "cap_gb": cap_gb})
+        log(f"serving qps={qps:.0f}: p50 {summ['p50_ms']:.2f} ms p99 {summ['p99_ms']:.2f} ms "
+            f"{summ['cells_per_s'] / 1e9:.1f} Gcells/s; one at a time p50 "
+            f"{summ['one_at_a_time']['p50_ms']:.2f} p99 {summ['one_at_a_time']['p99_ms']:.2f} ms "
+            f"{summ['one_at_a_time']['cells_per_s'] / 1e9:.1f} Gcells/s")
+        results.append(summ)
+        del ex
+        torch.cuda.empty_cache()
+    return {"tune": tune.as_dict(), "requests": count, "by_qps": results}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +293,11 @@ def main():
     ap.add_argument("--skip-single", action="store_true",
                     help="skip the one-launch-per-generation sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the diffusion, batched and serving legs")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--serve-qps", type=float, nargs="*", default=[1000.0, 4000.0, 16000.0])
+    ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -197,6 +395,18 @@ def main():
                 "algorithmic_bytes_per_launch": round(launch_bytes),
                 "launch_duration_us": round(launch_us, 2), "launches": launches}
 
+    extras = {}
+    if not args.no_extras:
+        del A, B
+        torch.cuda.empty_cache()
+        extras["sweep_one_launch_per_step"] = bench_sweep(torch, sg, inputs, (10, 12, 14),
+                                                          (4, 8, 16, 32, 64, 128, 256), 100)
+        extras["diffusion"] = bench_diffusion(torch, sg, inputs, (16, 64, 128, 256), args.steps, args.warmup)
+        extras["batched"] = bench_batched(torch, sg, inputs, args.batch_count, 50, 5)
+        torch.cuda.empty_cache()
+        extras["serving"] = bench_serving(torch, sg, inputs, args.serve_qps, args.serve_requests, 200.0)
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle (r=16 generations, >= 10 s)")
@@ -245,6 +455,7 @@ def main():
             "paper_context": PAPER_BEST_VS_BEST,
         },
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
 
 

@@ -145,6 +145,22 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
 SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in,
                            float *d_out, float alpha, void *stream);
 
+/* `steps` diffusion steps (sg_diffuse_step) with the result in d_out, in
+ * passes of up to `steps_per_pass` steps: a pass reads its tile plus a halo
+ * of that many cells from HBM once and runs the steps on chip (temporal
+ * blocking).  Every cell update is the same FP32 arithmetic as
+ * sg_diffuse_step, so the result equals `steps` calls of it bit for bit.
+ *   steps_per_pass: 1 (one launch per step, any rho), 2..8 (rho = 64), or 0
+ *     for the library's choice (8 where supported, else 1).
+ *   d_in: read only.  d_out: the state after `steps` steps.  d_work: a third
+ *     n * n float buffer, used when more than one pass runs (may be NULL
+ *     otherwise).  All: device, 16-byte aligned, pairwise non-overlapping,
+ *     0 off the gasket.  steps = 0 copies d_in to d_out.
+ * Errors: SG_EINVAL, SG_EALIAS, SG_EHIP. */
+SG_API int sg_diffuse_steps(int map, int r, int rho, int steps, int steps_per_pass,
+                            const float *d_in, float *d_out, float *d_work, float alpha,
+                            void *stream);
+
 /* ---------------------------------------------------------------------
  * Many gaskets at once (a batch of independent embedded gaskets of uneven
  * levels).  Every entry point below runs the temporally blocked life pass of
@@ -153,7 +169,8 @@ SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in,
  * --------------------------------------------------------------------- */
 
 /* Launch shape of a batched pass.
- *   rho:            lambda tile side, 64, 128 or 256 (<= every gasket's n)
+ *   rho:            largest lambda tile side, 64, 128 or 256; a gasket of
+ *                   side n < rho uses tiles of side n (gaskets need n >= 64)
  *   steps_per_pass: generations per pass, 1..16
  *   groups_per_cu:  persistent workgroups per compute unit, 1..64, or 0 for
  *                   one workgroup per tile
@@ -197,7 +214,7 @@ SG_API int sg_tune_default(sg_tune *tune);
  * all passes (and a device copy in -> out for gaskets with steps = 0) into a
  * hipGraph.  Allocates; not for the hot path.  The gaskets' buffers must stay
  * valid while the handle is used.
- * Errors: SG_EINVAL (bad shape, r < log2 rho, missing work buffer),
+ * Errors: SG_EINVAL (bad shape, r < 6 or r > SG_MAX_R, missing work buffer),
  * SG_EALIAS, SG_ENOMEM, SG_EHIP. */
 SG_API int sg_batch_create(const sg_gasket *gaskets, int count, const sg_tune *tune,
                            sg_batch **out);
@@ -214,8 +231,8 @@ SG_API int sg_batch_stats(const sg_batch *batch, uint64_t *passes, uint64_t *cel
 /* Frees the handle, its graph and its device tables (NULL is ignored). */
 SG_API void sg_batch_destroy(sg_batch *batch);
 
-/* Times every candidate shape (rho in {64, 128, 256} not above the smallest
- * gasket, 8 or 16 generations per pass, 0/2/4/8 groups per compute unit,
+/* Times every candidate shape (rho in {64, 128, 256}, 8 or 16 generations
+ * per pass, 0/2/4/8 groups per compute unit,
  * 256/512 threads) by running the batch on `stream` (writes the gaskets'
  * out/work buffers, never their inputs) and returns the fastest shape and
  * its time.  Synchronises the stream.  Errors as sg_batch_create. */
@@ -230,7 +247,7 @@ SG_API int sg_pass_ctx_create(int capacity, sg_pass_ctx **out);
 /* One batched pass over `count` items (host array, validated, then uploaded
  * asynchronously on `stream`).  Successive calls on one context must use
  * the same stream.  Errors: SG_EINVAL (count > capacity, steps outside
- * 0..steps_per_pass, r < log2 rho), SG_EALIAS, SG_EHIP. */
+ * 0..steps_per_pass, r < 6 or r > SG_MAX_R), SG_EALIAS, SG_EHIP. */
 SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
                        const sg_tune *tune, void *stream);
 

@@ -1,5 +1,6 @@
 // C entry points of libsg: argument validation (host only, before any HIP
 // call), map/tile bookkeeping, and dispatch to the kernel launchers.
+#include <stdlib.h>
 #include <string.h>
 
 #include "../../include/sg.h"
@@ -61,6 +62,19 @@ int pass_args(int map, int r, int rho, void *stream, sg::PassArgs &a) {
 
 }  // namespace
 
+namespace sg {
+bool inject_hip_error() {
+  static const bool on = getenv("SG_INJECT_HIP_ERROR") != nullptr;
+  return on;
+}
+}  // namespace sg
+
+#define SG_INJECT()                      \
+  do {                                   \
+    if (sg::inject_hip_error())          \
+      return hip_status(hipErrorLaunchFailure); \
+  } while (0)
+
 extern "C" {
 
 SG_API const char *sg_strerror(int code) {
@@ -98,12 +112,14 @@ SG_API int sg_block_count(int map, int r, int rho, uint64_t *blocks) {
 SG_API int sg_map_lambda(int r, int rho, uint32_t *d_bxy, void *stream) {
   const int rb = block_level(r, rho);
   if (rb < 0 || !d_bxy || ((uintptr_t)d_bxy & 7u)) return SG_EINVAL;
+  SG_INJECT();
   return hip_status(sg::launch_map_lambda(rb, (uint32_t)pow3(rb), d_bxy, (hipStream_t)stream));
 }
 
 SG_API int sg_map_bbox(int r, int rho, uint8_t *d_mask, void *stream) {
   const int rb = block_level(r, rho);
   if (rb < 0 || !d_mask) return SG_EINVAL;
+  SG_INJECT();
   return hip_status(sg::launch_map_bbox(rb, 1ull << (2 * rb), d_mask, (hipStream_t)stream));
 }
 
@@ -112,6 +128,7 @@ SG_API int sg_write_pass(int map, int r, int rho, uint8_t *d_a, uint8_t value, v
   const int st = pass_args(map, r, rho, stream, a);
   if (st != SG_OK) return st;
   if (!d_a || misaligned(d_a)) return SG_EINVAL;
+  SG_INJECT();
   return hip_status(sg::launch_write(a, d_a, value));
 }
 
@@ -123,6 +140,7 @@ SG_API int sg_ca_step(int map, int r, int rho, const uint8_t *d_in, uint8_t *d_o
   if (!d_in || !d_out || misaligned(d_in) || misaligned(d_out)) return SG_EINVAL;
   const size_t bytes = ((size_t)1 << r) * ((size_t)1 << r);
   if (overlaps(d_in, d_out, bytes)) return SG_EALIAS;
+  SG_INJECT();
   return hip_status(sg::launch_life(a, d_in, d_out));
 }
 
@@ -143,6 +161,7 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
     if (!d_work || misaligned(d_work)) return SG_EINVAL;
     if (overlaps(d_work, d_in, bytes) || overlaps(d_work, d_out, bytes)) return SG_EALIAS;
   }
+  SG_INJECT();
   if (steps == 0)
     return hip_status(hipMemcpyAsync(d_out, d_in, bytes, hipMemcpyDeviceToDevice, a.stream));
   // the last pass must land in d_out: alternate d_out / d_work backwards
@@ -158,6 +177,40 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
   return SG_OK;
 }
 
+SG_API int sg_diffuse_steps(int map, int r, int rho, int steps, int steps_per_pass,
+                            const float *d_in, float *d_out, float *d_work, float alpha,
+                            void *stream) {
+  sg::PassArgs a;
+  const int st = pass_args(map, r, rho, stream, a);
+  if (st != SG_OK) return st;
+  if (steps < 0 || steps_per_pass < 0 || steps_per_pass > sg::kMaxDiffuseStepsPerPass)
+    return SG_EINVAL;
+  const bool tb_ok = sg::diffuse_tb_supported(rho);
+  if (steps_per_pass == 0) steps_per_pass = tb_ok ? sg::kMaxDiffuseStepsPerPass : 1;
+  if (steps_per_pass > 1 && !tb_ok) return SG_EINVAL;
+  if (!d_in || !d_out || misaligned(d_in) || misaligned(d_out)) return SG_EINVAL;
+  const size_t bytes = ((size_t)1 << r) * ((size_t)1 << r) * sizeof(float);
+  if (overlaps(d_in, d_out, bytes)) return SG_EALIAS;
+  const int passes = (steps + steps_per_pass - 1) / steps_per_pass;
+  if (passes >= 2) {
+    if (!d_work || misaligned(d_work)) return SG_EINVAL;
+    if (overlaps(d_work, d_in, bytes) || overlaps(d_work, d_out, bytes)) return SG_EALIAS;
+  }
+  SG_INJECT();
+  if (steps == 0)
+    return hip_status(hipMemcpyAsync(d_out, d_in, bytes, hipMemcpyDeviceToDevice, a.stream));
+  const float *src = d_in;
+  for (int k = 1; k <= passes; ++k) {
+    float *dst = ((passes - k) % 2 == 0) ? d_out : d_work;
+    const int T = k < passes ? steps_per_pass : steps - (passes - 1) * steps_per_pass;
+    const hipError_t e = steps_per_pass == 1 ? sg::launch_diffuse(a, src, dst, alpha)
+                                             : sg::launch_diffuse_tb(a, T, src, dst, alpha);
+    if (e != hipSuccess) return hip_status(e);
+    src = dst;
+  }
+  return SG_OK;
+}
+
 SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in, float *d_out,
                            float alpha, void *stream) {
   sg::PassArgs a;
@@ -166,6 +219,7 @@ SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in, float *d_
   if (!d_in || !d_out || misaligned(d_in) || misaligned(d_out)) return SG_EINVAL;
   const size_t bytes = ((size_t)1 << r) * ((size_t)1 << r) * sizeof(float);
   if (overlaps(d_in, d_out, bytes)) return SG_EALIAS;
+  SG_INJECT();
   return hip_status(sg::launch_diffuse(a, d_in, d_out, alpha));
 }
 

@@ -83,9 +83,14 @@ struct Plan {
   uint64_t cell_steps = 0;                // sum of 3^r * steps
 };
 
-int validate_gasket(const sg_gasket &g, int rho) {
-  const int k = rho_log2(rho);
-  if (g.r < k || g.r > SG_MAX_R || g.steps < 0) return SG_EINVAL;
+// Tile side of a gasket of level r in a batch whose largest side is 2^kmax:
+// the largest supported side (64..2^kmax) that fits in the gasket.
+int item_k(int r, int kmax) { return r < kmax ? r : kmax; }
+
+constexpr int kMinTileLog2 = 6;  // smallest temporally blocked tile: 64
+
+int validate_gasket(const sg_gasket &g) {
+  if (g.r < kMinTileLog2 || g.r > SG_MAX_R || g.steps < 0) return SG_EINVAL;
   if (!g.in || !g.out || misaligned(g.in) || misaligned(g.out)) return SG_EINVAL;
   const size_t bytes = ((size_t)1 << g.r) * ((size_t)1 << g.r);
   if (overlaps(g.in, g.out, bytes)) return SG_EALIAS;
@@ -94,11 +99,11 @@ int validate_gasket(const sg_gasket &g, int rho) {
 
 int make_plan(const sg_gasket *gs, int count, const sg_tune &t, Plan &plan) {
   if (!gs || count < 1) return SG_EINVAL;
-  const int T = t.steps_per_pass, k = rho_log2(t.rho);
+  const int T = t.steps_per_pass, kmax = rho_log2(t.rho);
   int max_passes = 0;
   for (int i = 0; i < count; ++i) {
     const sg_gasket &g = gs[i];
-    int st = validate_gasket(g, t.rho);
+    int st = validate_gasket(g);
     if (st != SG_OK) return st;
     const int P = (g.steps + T - 1) / T;
     if (P >= 2) {
@@ -122,9 +127,10 @@ int make_plan(const sg_gasket *gs, int count, const sg_tune &t, Plan &plan) {
       it.src = p == 0 ? g.in : prev;
       it.dst = ((P - 1 - p) % 2 == 0) ? g.out : g.work;
       it.r = g.r;
-      it.steps = p < P - 1 ? T : g.steps - (P - 1) * T;
+      it.steps = (int16_t)(p < P - 1 ? T : g.steps - (P - 1) * T);
+      it.k = (int16_t)item_k(g.r, kmax);
       it.tile_begin = pass.total_tiles;
-      pass.total_tiles += pow3(g.r - k);
+      pass.total_tiles += pow3(g.r - it.k);
       pass.max_steps = std::max(pass.max_steps, (int)it.steps);
       pass.items.push_back(it);
     }
@@ -241,11 +247,13 @@ SG_API int sg_batch_create(const sg_gasket *gaskets, int count, const sg_tune *t
 
 SG_API int sg_batch_run(sg_batch *b, void *stream) {
   if (!b || !b->exec) return SG_EINVAL;
+  if (sg::inject_hip_error()) return SG_EHIP;
   return hip_err(hipGraphLaunch(b->exec, (hipStream_t)stream));
 }
 
 SG_API int sg_batch_run_eager(sg_batch *b, void *stream) {
   if (!b) return SG_EINVAL;
+  if (sg::inject_hip_error()) return SG_EHIP;
   return launch_plan(b->plan, b->tune, b->d_tables, b->offsets, (hipStream_t)stream);
 }
 
@@ -268,8 +276,6 @@ SG_API int sg_batch_autotune(const sg_gasket *gaskets, int count, sg_tune *best,
                              float *best_ms, void *stream) {
   if (!best) return SG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  int min_r = SG_MAX_R;
-  for (int i = 0; gaskets && i < count; ++i) min_r = std::min(min_r, gaskets[i].r);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -279,7 +285,6 @@ SG_API int sg_batch_autotune(const sg_gasket *gaskets, int count, sg_tune *best,
   int st_any = SG_EINVAL;
   const int rhos[] = {64, 128, 256}, spps[] = {8, 16}, gpcs[] = {0, 2, 4, 8}, thr[] = {256, 512};
   for (int rho : rhos) {
-    if (rho_log2(rho) > min_r) continue;
     for (int spp : spps)
       for (int gpc : gpcs)
         for (int th : thr) {
@@ -344,20 +349,21 @@ SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
   if (!ctx || count < 0 || count > ctx->capacity || (count > 0 && !items)) return SG_EINVAL;
   int st = check_tune(tune);
   if (st != SG_OK) return st;
-  const int k = rho_log2(tune->rho);
+  const int kmax = rho_log2(tune->rho);
   // validate everything before touching the staging buffer or the device
   int live = 0, max_steps = 0;
   for (int i = 0; i < count; ++i) {
     const sg_pass_item &it = items[i];
     if (it.steps < 0 || it.steps > tune->steps_per_pass) return SG_EINVAL;
     if (it.steps == 0) continue;
-    if (it.r < k || it.r > SG_MAX_R || !it.src || !it.dst) return SG_EINVAL;
+    if (it.r < kMinTileLog2 || it.r > SG_MAX_R || !it.src || !it.dst) return SG_EINVAL;
     if (misaligned(it.src) || misaligned(it.dst)) return SG_EINVAL;
     if (overlaps(it.src, it.dst, ((size_t)1 << it.r) * ((size_t)1 << it.r))) return SG_EALIAS;
     ++live;
     max_steps = std::max(max_steps, (int)it.steps);
   }
   if (live == 0) return SG_OK;
+  if (sg::inject_hip_error()) return SG_EHIP;
   hipStream_t s = (hipStream_t)stream;
   if (ctx->pending && hipEventSynchronize(ctx->staged) != hipSuccess) return SG_EHIP;
   uint64_t tiles = 0;
@@ -369,9 +375,10 @@ SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
     b.src = it.src;
     b.dst = it.dst;
     b.r = it.r;
-    b.steps = it.steps;
+    b.steps = (int16_t)it.steps;
+    b.k = (int16_t)item_k(it.r, kmax);
     b.tile_begin = tiles;
-    tiles += pow3(it.r - k);
+    tiles += pow3(it.r - b.k);
     ctx->h_stage[m++] = b;
   }
   st = hip_err(hipMemcpyAsync(ctx->d_items, ctx->h_stage, (size_t)m * sizeof(sg::BatchItem),

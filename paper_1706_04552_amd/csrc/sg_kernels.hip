@@ -279,12 +279,7 @@ __global__ __launch_bounds__(kWG) void k_diffuse(const float *__restrict__ in,
     const bool ms = has_d && on_gasket(x, y + 1);
     const float w = (i == 0) ? cl : C.v[i - 1];
     const float e = (i == RHO - 1) ? cr : C.v[i + 1];
-    float s = 0.0f;
-    s += mw ? (w - u) : 0.0f;
-    s += me ? (e - u) : 0.0f;
-    s += mn ? (U.v[i] - u) : 0.0f;
-    s += ms ? (D.v[i] - u) : 0.0f;
-    O.v[i] = on_gasket(x, y) ? u + alpha * s : 0.0f;
+    O.v[i] = diffuse_cell(u, w, e, U.v[i], D.v[i], mw, me, mn, ms, on_gasket(x, y), alpha);
   }
   store_frow<RHO>(out + y * n + X0, O);
 }
@@ -448,12 +443,8 @@ __global__ __launch_bounds__((Strip<RHO, 4>::WGS)) void k_diffuse_strip(
       const bool me = xj + 1 < n && on_gasket(xj + 1, y);
       const bool mn = y > 0 && on_gasket(xj, y - 1);
       const bool ms = y + 1 < n && on_gasket(xj, y + 1);
-      float s = 0.0f;
-      s += mw ? (west - u) : 0.0f;
-      s += me ? (east - u) : 0.0f;
-      s += mn ? (w[i - 1].v[j] - u) : 0.0f;
-      s += ms ? (w[i + 1].v[j] - u) : 0.0f;
-      O.v[j] = on_gasket(xj, y) ? u + alpha * s : 0.0f;
+      O.v[j] = diffuse_cell(u, west, east, w[i - 1].v[j], w[i + 1].v[j], mw, me, mn, ms,
+                            on_gasket(xj, y), alpha);
     }
     constexpr size_t smask = ~(size_t)(Granules<4 * RHO>::STORE / 4 - 1);
     if (((x & smask) & y) == 0) store_frow<4>(out + y * n + x, O);

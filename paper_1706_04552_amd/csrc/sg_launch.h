@@ -7,6 +7,11 @@
 
 namespace sg {
 
+// Test hook: when the environment variable SG_INJECT_HIP_ERROR is set at
+// library load, every entry point that would launch work reports a launch
+// failure (SG_EHIP) instead, after validating its arguments.
+bool inject_hip_error();
+
 // One pass over the tiles of a map.
 struct PassArgs {
   int r;            // level: n = 2^r
@@ -29,16 +34,25 @@ constexpr int kMaxStepsPerPass = 16;
 bool life_tb_supported(int rho);
 hipError_t launch_life_tb(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
 
+// Temporally blocked FP32 diffusion: T steps per pass, T in
+// [1, kMaxDiffuseStepsPerPass], for tile side rho = 64.
+constexpr int kMaxDiffuseStepsPerPass = 8;
+bool diffuse_tb_supported(int rho);
+hipError_t launch_diffuse_tb(const PassArgs &a, int T, const float *in, float *out,
+                             float alpha);
+
 // One pass over many gaskets (device table of items, sorted by tile_begin,
 // every item with at least one tile and 1 <= steps <= max_steps).
 struct BatchItem {
   const uint8_t *src;   // state before the pass
   uint8_t *dst;         // state after the pass
   uint64_t tile_begin;  // global index of the item's first lambda tile
-  int32_t r;            // level: n = 2^r (r >= log2 rho)
-  int32_t steps;        // generations in this pass
+  int32_t r;            // level: n = 2^r (r >= k)
+  int16_t steps;        // generations in this pass
+  int16_t k;            // this item's tile side is 2^k: 6, 7 or 8 (64, 128, 256)
 };
-hipError_t launch_life_tb_batch(int rho, int threads, const BatchItem *d_items, int count,
+// Tiles of every side up to max_rho may appear in one launch.
+hipError_t launch_life_tb_batch(int max_rho, int threads, const BatchItem *d_items, int count,
                                 uint64_t total_tiles, int max_steps, int groups,
                                 hipStream_t stream);
 

@@ -132,11 +132,15 @@ __device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
                                         uint32_t by, int T, uint32_t *lds, uint32_t *nseg_p) {
   uint32_t &nseg = *nseg_p;
   constexpr int kTbThreads = NT;
-  constexpr int W = RHO / 32 + 2;     // region words per row
+  // Region columns [X0-16, X0+RHO+16): the tile plus one 16-cell chunk each
+  // side, in W words of 32 cells; word w starts at X0 - 16 + 32w, so its low
+  // and high halves each start on a multiple of 16.
+  constexpr int W = RHO / 32 + 1;     // region words per row
   constexpr int PW = plane_pitch(W);  // plane pitch (at least one zero guard word each side)
-  constexpr int CH = RHO / 16 + 2;    // loaded 16-byte chunks per region row
+  constexpr int CH = 2 * W;           // 16-byte chunks per region row
   constexpr int L = kSegRows;
   static_assert(L <= 8, "row bits of a segment are kept in 8 bits");
+  static_assert(RHO % 64 == 0, "tiles span whole 64-byte granules");
   const int R = RHO + 2 * T;          // region rows
   const int NB = (R + L - 1) / L;     // segment blocks per word column
   const int RP = NB * L;              // region rows rounded up to whole blocks
@@ -150,13 +154,14 @@ __device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
 
   uint32_t *plane0 = lds;
   uint32_t *plane1 = lds + PR * PW;
-  uint32_t *rowpat = plane1 + PR * PW;  // RP: gasket pattern of each region row
+  uint32_t *rowpat = plane1 + PR * PW;  // RP: gasket pattern of each region row (both halves)
   uint32_t *segs = rowpat + RP;         // W * NB: listed segments
 
   for (int i = tid; i < 2 * PR * PW; i += kTbThreads) lds[i] = 0u;
   for (int i = tid; i < RP; i += kTbThreads) {
     const int y = yr0 + i;
-    rowpat[i] = (i < R && y >= 0 && y < n) ? word_pattern((uint32_t)y) : 0u;
+    const uint32_t p16 = word_pattern((uint32_t)y & 15u) & 0xFFFFu;
+    rowpat[i] = (i < R && y >= 0 && y < n) ? (p16 | (p16 << 16)) : 0u;
   }
   if (tid == 0) nseg = 0u;
   __syncthreads();
@@ -176,7 +181,7 @@ __device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
         const int y = yr0 + i, x = X0 - 16 + 16 * j;
         if (y >= 0 && y < n && x >= 0 && x < n && (x & y) == 0) {
           v[q] = *reinterpret_cast<const uint4 *>(in + (size_t)y * n + x);
-          slot[q] = ((i + 1) * PW + (((j + 1) >> 1) + 1)) * 2 + ((j + 1) & 1);
+          slot[q] = ((i + 1) * PW + ((j >> 1) + 1)) * 2 + (j & 1);
         }
       }
     }
@@ -186,23 +191,25 @@ __device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
   }
 
   // 2. compact list of the segments (word column w, rows [b*L, b*L+L)) that
-  //    hold a gasket cell, listed column by column; each entry keeps the
-  //    rows whose word starts on the gasket (x & y == 0 for its first cell)
+  //    hold a gasket cell, listed column by column; each entry keeps, per row
+  //    and per half word, whether that half's first cell is on the gasket
+  //    (then its cells are exactly those with (i & y) == 0)
   const int lane = __lane_id();
   for (int base = 0; base < W * NB; base += kTbThreads) {
     const int e = base + tid;
     uint32_t rows = 0u, code = 0u;
     if (e < W * NB) {
       const int w = e / NB, b = e - (e / NB) * NB;
-      const int xw = X0 - 32 + 32 * w;
-      if (xw >= 0 && xw < n) {
+      const int xlo = X0 - 16 + 32 * w, xhi = xlo + 16;
+      const bool lo_in = xlo >= 0 && xlo < n, hi_in = xhi < n;
 #pragma unroll
-        for (int q = 0; q < L; ++q) {
-          const int i = b * L + q;
-          if (rowpat[i] != 0u && (xw & (yr0 + i)) == 0) rows |= 1u << q;
-        }
+      for (int q = 0; q < L; ++q) {
+        const int i = b * L + q, y = yr0 + i;
+        if (rowpat[i] == 0u) continue;
+        if (lo_in && (xlo & y) == 0) rows |= 1u << q;
+        if (hi_in && (xhi & y) == 0) rows |= 1u << (q + 8);
       }
-      code = (uint32_t)w | ((uint32_t)b << 8) | (rows << 24);
+      code = (uint32_t)w | ((uint32_t)b << 8) | (rows << 16);
     }
     const uint64_t ball = __ballot(rows != 0u);
     const uint32_t before = (uint32_t)__popcll(ball & ((1ull << lane) - 1ull));
@@ -218,14 +225,18 @@ __device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
   for (int s = 0; s < T; ++s) {
     const uint32_t *src = (s & 1) ? plane1 : plane0;
     uint32_t *dst = (s & 1) ? plane0 : plane1;
+    // rows that can still reach the tile in the T-s-1 generations left:
+    // region rows [s+1, R-s-1); segments wholly outside are skipped
+    const int lo_row = s + 1, hi_row = R - s - 1;
     for (int k = tid; k < ns; k += kTbThreads) {
       const uint32_t code = segs[k];
-      const int w = (int)(code & 0xffu), i0 = (int)((code >> 8) & 0xffffu) * L;
-      const uint32_t rows = code >> 24;
+      const int w = (int)(code & 0xffu), i0 = (int)((code >> 8) & 0xffu) * L;
+      if (i0 + L <= lo_row || i0 >= hi_row) continue;
+      const uint32_t rows = code >> 16;
       const int idx0 = (i0 + 1) * PW + (w + 1);
       // all rows the segment reads, before any store (the planes may alias as
       // far as the compiler knows, so loads are not moved past stores)
-      uint32_t row[L + 2][3];
+      uint32_t row[L + 2][3], pat[L];
 #pragma unroll
       for (int q = 0; q < L + 2; ++q) {
         const uint32_t *p = src + idx0 + (q - 1) * PW;
@@ -233,12 +244,16 @@ __device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
         row[q][1] = p[0];
         row[q][2] = p[1];
       }
+#pragma unroll
+      for (int q = 0; q < L; ++q) pat[q] = rowpat[i0 + q];
       RowSums up = row_sums(row[0][0], row[0][1], row[0][2]);
       RowSums mid = row_sums(row[1][0], row[1][1], row[1][2]);
 #pragma unroll
       for (int q = 0; q < L; ++q) {
         const RowSums dn = row_sums(row[q + 2][0], row[q + 2][1], row[q + 2][2]);
-        const uint32_t m = rowpat[i0 + q] & (0u - ((rows >> q) & 1u));
+        const uint32_t lo = (0u - ((rows >> q) & 1u)) & 0x0000FFFFu;
+        const uint32_t hi = (0u - ((rows >> (q + 8)) & 1u)) & 0xFFFF0000u;
+        const uint32_t m = pat[q] & (lo | hi);
         dst[idx0 + q * PW] = life_rule(up, mid, dn) & m;
         up = mid;
         mid = dn;
@@ -254,7 +269,7 @@ __device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
     const int ty = e / TC, j = e - (e / TC) * TC;
     const int y = Y0 + ty, x = X0 + 16 * j;
     if (((x & ~63) & y) != 0) continue;
-    const int w = 1 + (j >> 1), half = j & 1;
+    const int w = (j + 1) >> 1, half = (j + 1) & 1;  // region chunk j + 1
     const uint32_t bits = fin[((T + ty + 1) * PW + (w + 1)) * 2 + half];
     *reinterpret_cast<uint4 *>(out + (size_t)y * n + x) = unpack16(bits);
   }
@@ -284,14 +299,14 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__
 // Many gaskets in one persistent launch: workgroups stride over the global
 // tile index of all items (each item's lambda tiles numbered from its
 // tile_begin, items sorted by tile_begin), find the item by a binary search
-// (uniform per workgroup, so it runs on the scalar unit) and run the same
-// tile pass on that item's buffers with that item's generation count.
-template <int RHO, int NT>
+// (uniform per workgroup, so it runs on the scalar unit) and run the tile
+// pass on that item's buffers, with that item's tile side (up to MAXRHO) and
+// generation count.
+template <int MAXRHO, int NT>
 __global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restrict__ items,
                                                       int count, uint64_t total_tiles) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t nseg;
-  constexpr int K = rho_log2_const(RHO);
   for (uint64_t g = blockIdx.x; g < total_tiles; g += gridDim.x) {
     int lo = 0, hi = count - 1;
     while (lo < hi) {
@@ -300,15 +315,21 @@ __global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restric
     }
     const BatchItem it = items[lo];
     uint32_t bx, by;
-    lambda_decode((uint32_t)(g - it.tile_begin), it.r - K, bx, by);
-    tb_tile<RHO, NT>(it.src, it.dst, it.r, bx, by, it.steps, lds, &nseg);
+    lambda_decode((uint32_t)(g - it.tile_begin), it.r - it.k, bx, by);
+    if (it.k == 6) {
+      tb_tile<64, NT>(it.src, it.dst, it.r, bx, by, it.steps, lds, &nseg);
+    } else if (MAXRHO >= 128 && it.k == 7) {
+      tb_tile<(MAXRHO >= 128 ? 128 : 64), NT>(it.src, it.dst, it.r, bx, by, it.steps, lds, &nseg);
+    } else if (MAXRHO >= 256 && it.k == 8) {
+      tb_tile<(MAXRHO >= 256 ? 256 : 64), NT>(it.src, it.dst, it.r, bx, by, it.steps, lds, &nseg);
+    }
     __syncthreads();  // the next tile reuses the LDS planes
   }
 }
 
 template <int RHO>
 size_t tb_lds_bytes(int T) {
-  const int W = RHO / 32 + 2, PW = plane_pitch(W), R = RHO + 2 * T;
+  const int W = RHO / 32 + 1, PW = plane_pitch(W), R = RHO + 2 * T;
   const int NB = (R + kSegRows - 1) / kSegRows, RP = NB * kSegRows, PR = RP + 2;
   return sizeof(uint32_t) * (size_t)(2 * PR * PW + RP + W * NB);
 }
@@ -334,6 +355,7 @@ hipError_t life_tb_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out
 template <int RHO, int NT>
 hipError_t life_tb_batch_rho(const BatchItem *d_items, int count, uint64_t total_tiles,
                              int max_steps, int groups, hipStream_t stream) {
+  // the largest tile side needs the most LDS
   const size_t lds = tb_lds_bytes<RHO>(max_steps);
   const uint64_t g = total_tiles < (uint64_t)groups ? total_tiles : (uint64_t)groups;
   if (g == 0) return hipSuccess;
@@ -344,13 +366,13 @@ hipError_t life_tb_batch_rho(const BatchItem *d_items, int count, uint64_t total
 
 }  // namespace
 
-hipError_t launch_life_tb_batch(int rho, int threads, const BatchItem *d_items, int count,
+hipError_t launch_life_tb_batch(int max_rho, int threads, const BatchItem *d_items, int count,
                                 uint64_t total_tiles, int max_steps, int groups,
                                 hipStream_t stream) {
   if (max_steps < 1 || max_steps > kMaxStepsPerPass || groups < 1) return hipErrorInvalidValue;
   const bool t512 = threads == 512;
   if (threads != 256 && threads != 512) return hipErrorInvalidValue;
-  switch (rho) {
+  switch (max_rho) {
     case 64: return t512 ? life_tb_batch_rho<64, 512>(d_items, count, total_tiles, max_steps, groups, stream)
                          : life_tb_batch_rho<64, 256>(d_items, count, total_tiles, max_steps, groups, stream);
     case 128: return t512 ? life_tb_batch_rho<128, 512>(d_items, count, total_tiles, max_steps, groups, stream)

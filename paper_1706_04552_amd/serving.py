@@ -86,13 +86,19 @@ class ContinuousBatcher:
 
     def __init__(self, executor, cap_bytes: int, steps_per_pass: int,
                  keep_outputs: bool = False, clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep,
+                 max_cells_per_pass: Optional[int] = None):
+        """max_cells_per_pass: optional budget of cell updates per iteration;
+        resident requests join a pass in admission order until it is spent
+        (at least one always runs), so earlier requests finish first while
+        small ones still share passes."""
         self.ex = executor
         self.cap = cap_bytes
         self.T = steps_per_pass
         self.keep_outputs = keep_outputs
         self.clock = clock
         self.sleep = sleep
+        self.budget = max_cells_per_pass
 
     def serve(self, requests: Sequence[Request]) -> ServeStats:
         """Serve `requests` (arrival times in seconds after the start)."""
@@ -131,8 +137,16 @@ class ContinuousBatcher:
                     if wait > 0:
                         self.sleep(min(wait, 0.001))
                 continue
-            # one batched pass over every resident request
-            work = [(s.handle, min(self.T, s.remaining)) for s in active]
+            # one batched pass over the resident requests (in admission order,
+            # within the optional budget)
+            work, spent = [], 0
+            for s in active:
+                k = min(self.T, s.remaining)
+                cost = (3 ** s.req.r) * k
+                if work and self.budget is not None and spent + cost > self.budget:
+                    k = 0
+                spent += cost if k else 0
+                work.append((s.handle, k))
             self.ex.run_pass(work)
             self.ex.sync()
             st.iterations += 1
@@ -164,16 +178,24 @@ class GpuExecutor:
         self.tune = tune
         self.ctx = PassContext(capacity)
         self.templates = templates or {}
+        # released buffers, by level: they hold 0 on every cell off the gasket
+        # (passes never write there), which is all a destination needs
+        self.pool: Dict[int, List[object]] = {}
+
+    def _buffer(self, r: int):
+        free = self.pool.get(r)
+        if free:
+            return free.pop()
+        n = 1 << r
+        return self.torch.zeros((n, n), dtype=self.torch.uint8, device="cuda")
 
     def admit(self, q: Request):
-        torch = self.torch
-        n = 1 << q.r
+        cur = self._buffer(q.r)
         if q.template is not None:
-            cur = self.templates[q.template].clone()
+            cur.copy_(self.templates[q.template])
         else:
-            cur = torch.from_numpy(np.ascontiguousarray(q.state)).cuda()
-        nxt = torch.zeros((n, n), dtype=torch.uint8, device=cur.device)
-        return {"r": q.r, "buf": [cur, nxt]}
+            cur.copy_(self.torch.from_numpy(np.ascontiguousarray(q.state)))
+        return {"r": q.r, "buf": [cur, self._buffer(q.r)]}
 
     def run_pass(self, work):
         items = []
@@ -191,6 +213,7 @@ class GpuExecutor:
         return h["buf"][0].cpu().numpy()
 
     def release(self, h):
+        self.pool.setdefault(h["r"], []).extend(h["buf"])
         h["buf"] = None
 
     def close(self):

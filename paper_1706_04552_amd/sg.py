@@ -58,6 +58,9 @@ _SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "sg_diffuse_step": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
+    "sg_diffuse_steps": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
     "sg_tune_default": (ctypes.c_int, [_tunep]),
     "sg_batch_create": (ctypes.c_int, [ctypes.POINTER(sg_gasket), ctypes.c_int, _tunep,
                                        ctypes.POINTER(_vp)]),
@@ -216,4 +219,17 @@ def sg_diffuse_step(map_kind, r: int, rho: int, d_in: torch.Tensor, d_out: torch
     po = _dev(d_out, torch.float32, n2, "d_out")
     _check(load().sg_diffuse_step(_map(map_kind), r, rho, pi, po, alpha, _stream(stream)),
            "sg_diffuse_step")
+    return d_out
+
+
+def sg_diffuse_steps(map_kind, r: int, rho: int, steps: int, d_in: torch.Tensor,
+                     d_out: torch.Tensor, d_work: Optional[torch.Tensor] = None,
+                     alpha: float = 0.2, steps_per_pass: int = 0, stream=None) -> torch.Tensor:
+    """`steps` diffusion steps from d_in into d_out (d_work: third buffer)."""
+    n2 = _n2(r)
+    pi = _dev(d_in, torch.float32, n2, "d_in")
+    po = _dev(d_out, torch.float32, n2, "d_out")
+    pw = _dev(d_work, torch.float32, n2, "d_work") if d_work is not None else None
+    _check(load().sg_diffuse_steps(_map(map_kind), r, rho, steps, steps_per_pass, pi, po, pw,
+                                   alpha, _stream(stream)), "sg_diffuse_steps")
     return d_out

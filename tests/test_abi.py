@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -190,3 +191,40 @@ def test_batch_api_validation_on_the_host(lib):
     item = (sg.sg_pass_item * 1)()
     assert lib.sg_pass_run(None, item, 1, ctypes.byref(good), None) == sg.SG_EINVAL
     lib.sg_pass_ctx_destroy(None)
+
+
+def test_hip_errors_surface_as_sg_ehip():
+    # a fresh process with the library's fault-injection hook switched on: every
+    # entry point validates its arguments, then reports SG_EHIP without launching
+    code = r"""
+import ctypes, sys
+sys.path.insert(0, %r)
+from paper_1706_04552_amd import sg
+lib = sg.load()
+a, b, w = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x7000000000), ctypes.c_void_p(0x7100000000)
+res = [lib.sg_ca_step(0, 8, 16, a, b, None), lib.sg_write_pass(1, 8, 16, a, 1, None),
+       lib.sg_diffuse_step(0, 8, 16, a, b, 0.2, None), lib.sg_map_lambda(8, 16, a, None),
+       lib.sg_map_bbox(8, 16, a, None), lib.sg_ca_steps(0, 8, 64, 20, 16, a, b, w, None),
+       lib.sg_ca_step(0, 8, 3, a, b, None)]
+print(res, lib.sg_last_hip_error().decode())
+""" % ROOT
+    env = dict(os.environ, SG_INJECT_HIP_ERROR="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    line = out.stdout.strip().splitlines()[-1]
+    res = eval(line.split("]")[0] + "]")
+    assert res[:6] == [-3] * 6 and res[6] == -1  # invalid arguments are still SG_EINVAL
+    assert line.split("]", 1)[1].strip()  # the HIP error text is kept
+
+
+def test_diffuse_steps_validation(lib):
+    from paper_1706_04552_amd import sg
+    a, b, w = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x7000000000), ctypes.c_void_p(0x7100000000)
+    r = 8
+    assert lib.sg_diffuse_steps(0, r, 64, 10, 9, a, b, w, 0.2, None) == sg.SG_EINVAL
+    assert lib.sg_diffuse_steps(0, r, 128, 10, 4, a, b, w, 0.2, None) == sg.SG_EINVAL
+    assert lib.sg_diffuse_steps(0, r, 64, -2, 4, a, b, w, 0.2, None) == sg.SG_EINVAL
+    assert lib.sg_diffuse_steps(0, r, 64, 10, 4, a, b, None, 0.2, None) == sg.SG_EINVAL
+    assert lib.sg_diffuse_steps(0, r, 64, 10, 4, a, ctypes.c_void_p(0x100000 + 4096), w, 0.2, None) == sg.SG_EALIAS
+    assert lib.sg_diffuse_steps(0, r, 64, 10, 4, a, b, ctypes.c_void_p(0x7000000000 + 16), 0.2, None) == sg.SG_EALIAS

@@ -271,3 +271,43 @@ def test_diffusion_full_size_sampled(rho):
     t0 = float(u0.astype(np.float64).sum())
     t1 = float(got.astype(np.float64).sum())
     assert abs(t1 - t0) <= DIFF_RTOL * t0
+
+
+# ------------------------------------------------------------------ multi-step diffusion
+
+@pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
+@pytest.mark.parametrize("r,steps,spp", [(6, 1, 8), (6, 8, 8), (7, 13, 8), (8, 30, 5), (9, 17, 3),
+                                         (10, 40, 8), (10, 0, 8), (8, 9, 1)])
+def test_diffuse_steps_equal_one_step_calls_and_oracle(map_kind, r, steps, spp):
+    note(f"diffuse_steps {map_kind} r={r} steps={steps} per_pass={spp}")
+    u0 = inputs.uniform_field(r, 1706 + 5 * r)
+    a = dev(u0)
+    out, work = torch.zeros_like(a), torch.zeros_like(a)
+    sg.sg_diffuse_steps(map_kind, r, 64, steps, a, out, work, 0.2, steps_per_pass=spp)
+    torch.cuda.synchronize()
+    one = gpu_diffuse(map_kind, r, 64, u0, steps)  # one launch per step
+    assert torch.equal(out, one)
+    ref = O.diffuse_steps(r, u0, steps)
+    max_abs, scale, rel_l2 = diff_errors(out.cpu().numpy(), ref)
+    assert max_abs <= DIFF_RTOL * scale and rel_l2 <= DIFF_RTOL
+
+
+def test_diffuse_steps_full_size_sampled():
+    r, rho, steps = 14, 64, 500
+    note(f"diffuse_steps full-size r={r} rho={rho} {steps} steps, 8 per pass")
+    n = 1 << r
+    u0 = inputs.uniform_field(r, 1706)
+    a = dev(u0)
+    out, work = torch.zeros_like(a), torch.zeros_like(a)
+    sg.sg_diffuse_steps("lambda", r, rho, steps, a, out, work, 0.2, steps_per_pass=8)
+    torch.cuda.synchronize()
+    one = gpu_diffuse("lambda", r, rho, u0, steps)
+    assert torch.equal(out, one)
+    got = out.cpu().numpy()
+    rng = np.random.default_rng(8)
+    refs, gots = [], []
+    for (x0, y0) in _windows(n, rng, 2, 8, 8):
+        refs.append(O.diffuse_window(r, u0, x0, y0, 8, 8, steps))
+        gots.append(got[y0:y0 + 8, x0:x0 + 8])
+    max_abs, scale, rel_l2 = diff_errors(np.concatenate(gots), np.concatenate(refs))
+    assert max_abs <= DIFF_RTOL * scale and rel_l2 <= DIFF_RTOL

