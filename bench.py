@@ -362,6 +362,23 @@ def main():
                     f"{cells / (ms * 1e-3) / 1e9:8.2f} Gcells/s")
     del Out, Work
 
+    # block-compacted storage: only the fractal tiles, (4/3)^k * 3^r bytes
+    compact = {}
+    for rho in [x for x in args.rho if x in TB_RHOS]:
+        size = sg.sg_compact_bytes(R, rho)
+        Cin = torch.empty(size, dtype=torch.uint8, device=dev)
+        sg.sg_compact_pack(R, rho, A, Cin)
+        Cout, Cwork = torch.empty_like(Cin), torch.empty_like(Cin)
+        for T in args.per_pass:
+            def run():
+                sg.sg_ca_steps_compact(R, rho, args.steps, Cin, Cout, Cwork, steps_per_pass=T)
+            ms = time_region(torch, run, 1, 1 if args.warmup else 0) / args.steps
+            compact[f"rho{rho}_T{T}"] = round(ms * 1e3, 3)
+            log(f"ca {T:2d}/pass   compact rho={rho:3d}: {ms * 1e3:9.2f} us/step  "
+                f"{cells / (ms * 1e-3) / 1e9:8.2f} Gcells/s  ({size / 2 ** 30:.2f} GiB state)")
+        compact[f"rho{rho}_state_gib"] = round(size / 2 ** 30, 3)
+        del Cin, Cout, Cwork
+
     cands = [((rho, 1), ms) for rho, ms in results["lambda"].items()]
     cands += list(multi["lambda"].items())
     (best_rho, best_T), best_ms = min(cands, key=lambda kv: kv[1])
@@ -376,6 +393,15 @@ def main():
             wp[map_kind][rho] = time_region(
                 torch, lambda: sg.sg_write_pass(map_kind, R, rho, Wt, 1), args.steps, args.warmup)
             log(f"write {map_kind:6s} rho={rho:3d}: {wp[map_kind][rho] * 1e3:9.2f} us")
+    # the paper's other intra-block mappings (one thread per gasket cell)
+    intra = {}
+    for variant in ("unroll", "lut"):
+        for map_kind in ("lambda", "bbox"):
+            for rho in [x for x in args.rho if x <= 32]:
+                ms = time_region(torch, lambda: sg.sg_write_pass_intra(map_kind, variant, R, rho, Wt, 1),
+                                 args.steps, args.warmup)
+                intra.setdefault(variant, {}).setdefault(map_kind, {})[str(rho)] = round(ms * 1e3, 3)
+                log(f"write {variant:6s} {map_kind:6s} rho={rho:3d}: {ms * 1e3:9.2f} us")
     del Wt
     wl = min(wp["lambda"], key=lambda k: wp["lambda"][k])
     wb = min(wp["bbox"], key=lambda k: wp["bbox"][k])
@@ -446,11 +472,14 @@ def main():
             "best_vs_best": round(bb_ms / best_ms, 3),
             "best": {"lambda": {"rho": best_rho, "steps_per_launch": best_T},
                      "bbox": {"rho": bb_rho, "steps_per_launch": bb_T}},
+            "compact_storage_us": compact,
+            "embedding_state_gib": round(n * n / 2 ** 30, 3),
         },
         "write_pass": {
             "us": {m: {str(k): round(v * 1e3, 3) for k, v in wp[m].items()} for m in wp},
             "best_vs_best": round(wp["bbox"][wb] / wp["lambda"][wl], 3),
             "best_rho": {"lambda": wl, "bbox": wb},
+            "intra_block_variants_us": intra,
             "lambda_cells_per_s": cells / (wp["lambda"][wl] * 1e-3),
             "paper_context": PAPER_BEST_VS_BEST,
         },

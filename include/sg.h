@@ -93,6 +93,12 @@ SG_API int sg_block_count(int map, int r, int rho, uint64_t *blocks);
  * d_bxy: device, 2 * 3^r_b uint32 (8-byte aligned).  Errors: SG_EINVAL. */
 SG_API int sg_map_lambda(int r, int rho, uint32_t *d_bxy, void *stream);
 
+/* Inverse of lambda: d_omega[by * n_b + bx] = the linear omega that
+ * sg_map_lambda sends to block (bx, by), or -1 if the block holds no gasket
+ * cell.  d_omega: device, n_b * n_b int32 (4-byte aligned).
+ * Errors: SG_EINVAL (also 3^r_b > 2^31 - 1). */
+SG_API int sg_map_lambda_inverse(int r, int rho, int32_t *d_omega, void *stream);
+
 /* Bounding-box map (Section I, Fig. 3): the identity over the n_b x n_b
  * block grid.  d_mask[by * n_b + bx] = 1 iff block (bx, by) keeps at least
  * one thread (holds a gasket cell), else 0.
@@ -105,6 +111,21 @@ SG_API int sg_map_bbox(int r, int rho, uint8_t *d_mask, void *stream);
  * d_a: device, n * n bytes, row-major.  Errors: SG_EINVAL. */
 SG_API int sg_write_pass(int map, int r, int rho, uint8_t *d_a, uint8_t value,
                          void *stream);
+
+/* Intra-block mapping of the threads of a block (Section III-D). */
+typedef enum sg_intra_kind {
+    SG_INTRA_SUBBOX = 0, /* bounding sub-boxes: every cell of the block, masked */
+    SG_INTRA_UNROLL = 1, /* further unrolling: lambda again at thread level */
+    SG_INTRA_LUT = 2     /* a shared lookup table of the in-block cell offsets */
+} sg_intra_kind;
+
+/* The write pass with a chosen intra-block mapping.  SG_INTRA_SUBBOX is
+ * sg_write_pass.  SG_INTRA_UNROLL and SG_INTRA_LUT launch only the 3^k
+ * threads per block that own a gasket cell (rho = 2^k <= 32) and store one
+ * byte each: cells off the gasket are never written.
+ * Errors: SG_EINVAL (also rho > 32 for UNROLL/LUT), SG_EHIP. */
+SG_API int sg_write_pass_intra(int map, int intra, int r, int rho, uint8_t *d_a,
+                               uint8_t value, void *stream);
 
 /* One generation of B3/S23 life on the gasket (an application of the
  * embedded gasket, Section I): for every gasket cell, c = number of live
@@ -160,6 +181,34 @@ SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in,
 SG_API int sg_diffuse_steps(int map, int r, int rho, int steps, int steps_per_pass,
                             const float *d_in, float *d_out, float *d_work, float alpha,
                             void *stream);
+
+/* ---------------------------------------------------------------------
+ * Block-compacted storage: only the 3^r_b fractal tiles of side rho (64,
+ * 128 or 256), tile omega (lambda order, as sg_map_lambda) stored at byte
+ * omega * rho^2 as rho rows of rho bytes -- (4/3)^k * 3^r bytes instead of
+ * the n^2 of the embedding.  A compact state holds 0 on the cells of its
+ * tiles that are off the gasket.
+ * --------------------------------------------------------------------- */
+
+/* Host only.  Bytes of a compact state: 3^r_b * rho^2. */
+SG_API int sg_compact_bytes(int r, int rho, uint64_t *bytes);
+
+/* Embedding (n * n bytes) -> compact state, and back.  Unpack writes the
+ * fractal tiles of d_dense whole and nothing else (the rest must be 0).
+ * Errors: SG_EINVAL, SG_EALIAS (the two arrays overlap), SG_EHIP. */
+SG_API int sg_compact_pack(int r, int rho, const uint8_t *d_dense, uint8_t *d_compact,
+                           void *stream);
+SG_API int sg_compact_unpack(int r, int rho, const uint8_t *d_compact, uint8_t *d_dense,
+                             void *stream);
+
+/* sg_ca_steps on compact states (lambda map): `steps` life generations
+ * from d_in into d_out, up to `steps_per_pass` (1..16, 0 = 16) per pass;
+ * every pass rewrites its output tiles whole, so d_out and d_work need no
+ * zeroing.  All three: compact-sized, 16-byte aligned, non-overlapping.
+ * Errors: SG_EINVAL, SG_EALIAS, SG_EHIP. */
+SG_API int sg_ca_steps_compact(int r, int rho, int steps, int steps_per_pass,
+                               const uint8_t *d_in, uint8_t *d_out, uint8_t *d_work,
+                               void *stream);
 
 /* ---------------------------------------------------------------------
  * Many gaskets at once (a batch of independent embedded gaskets of uneven

@@ -132,6 +132,19 @@ SG_API int sg_write_pass(int map, int r, int rho, uint8_t *d_a, uint8_t value, v
   return hip_status(sg::launch_write(a, d_a, value));
 }
 
+SG_API int sg_write_pass_intra(int map, int intra, int r, int rho, uint8_t *d_a, uint8_t value,
+                               void *stream) {
+  sg::PassArgs a;
+  const int st = pass_args(map, r, rho, stream, a);
+  if (st != SG_OK) return st;
+  if (intra != SG_INTRA_SUBBOX && intra != SG_INTRA_UNROLL && intra != SG_INTRA_LUT) return SG_EINVAL;
+  if (!d_a || misaligned(d_a)) return SG_EINVAL;
+  if (intra != SG_INTRA_SUBBOX && rho > 32) return SG_EINVAL;
+  SG_INJECT();
+  if (intra == SG_INTRA_SUBBOX) return hip_status(sg::launch_write(a, d_a, value));
+  return hip_status(sg::launch_write_intra(a, d_a, value, intra == SG_INTRA_LUT));
+}
+
 SG_API int sg_ca_step(int map, int r, int rho, const uint8_t *d_in, uint8_t *d_out,
                       void *stream) {
   sg::PassArgs a;
@@ -205,6 +218,81 @@ SG_API int sg_diffuse_steps(int map, int r, int rho, int steps, int steps_per_pa
     const int T = k < passes ? steps_per_pass : steps - (passes - 1) * steps_per_pass;
     const hipError_t e = steps_per_pass == 1 ? sg::launch_diffuse(a, src, dst, alpha)
                                              : sg::launch_diffuse_tb(a, T, src, dst, alpha);
+    if (e != hipSuccess) return hip_status(e);
+    src = dst;
+  }
+  return SG_OK;
+}
+
+SG_API int sg_map_lambda_inverse(int r, int rho, int32_t *d_omega, void *stream) {
+  const int rb = block_level(r, rho);
+  if (rb < 0 || !d_omega || ((uintptr_t)d_omega & 3u)) return SG_EINVAL;
+  if (pow3(rb) > 0x7fffffffull) return SG_EINVAL;  // omega must fit an int32
+  SG_INJECT();
+  return hip_status(sg::launch_map_lambda_inverse(rb, d_omega, (hipStream_t)stream));
+}
+
+SG_API int sg_compact_bytes(int r, int rho, uint64_t *bytes) {
+  const int rb = block_level(r, rho);
+  if (rb < 0 || !bytes || !sg::life_tb_supported(rho)) return SG_EINVAL;
+  *bytes = pow3(rb) * (uint64_t)rho * (uint64_t)rho;
+  return SG_OK;
+}
+
+namespace {
+int compact_copy(int r, int rho, const uint8_t *src, uint8_t *dst, bool pack, void *stream) {
+  sg::PassArgs a;
+  const int st = pass_args(SG_MAP_LAMBDA, r, rho, stream, a);
+  if (st != SG_OK) return st;
+  if (!sg::life_tb_supported(rho) || !src || !dst || misaligned(src) || misaligned(dst))
+    return SG_EINVAL;
+  const size_t dense = ((size_t)1 << r) * ((size_t)1 << r);
+  const size_t packed = (size_t)pow3(a.rb) * (size_t)rho * (size_t)rho;
+  const uint8_t *lo = src < dst ? src : dst;
+  const uint8_t *hi = src < dst ? dst : src;
+  const size_t lo_bytes = (lo == (pack ? src : dst)) ? dense : packed;
+  if ((uintptr_t)lo + lo_bytes > (uintptr_t)hi) return SG_EALIAS;
+  SG_INJECT();
+  return hip_status(sg::launch_compact_copy(a, pack, src, dst));
+}
+}  // namespace
+
+SG_API int sg_compact_pack(int r, int rho, const uint8_t *d_dense, uint8_t *d_compact,
+                           void *stream) {
+  return compact_copy(r, rho, d_dense, d_compact, true, stream);
+}
+
+SG_API int sg_compact_unpack(int r, int rho, const uint8_t *d_compact, uint8_t *d_dense,
+                             void *stream) {
+  return compact_copy(r, rho, d_compact, d_dense, false, stream);
+}
+
+SG_API int sg_ca_steps_compact(int r, int rho, int steps, int steps_per_pass,
+                               const uint8_t *d_in, uint8_t *d_out, uint8_t *d_work,
+                               void *stream) {
+  sg::PassArgs a;
+  const int st = pass_args(SG_MAP_LAMBDA, r, rho, stream, a);
+  if (st != SG_OK) return st;
+  if (!sg::life_tb_supported(rho) || steps < 0 || steps_per_pass < 0 ||
+      steps_per_pass > sg::kMaxStepsPerPass)
+    return SG_EINVAL;
+  if (steps_per_pass == 0) steps_per_pass = sg::kMaxStepsPerPass;
+  if (!d_in || !d_out || misaligned(d_in) || misaligned(d_out)) return SG_EINVAL;
+  const size_t bytes = (size_t)pow3(a.rb) * (size_t)rho * (size_t)rho;
+  if (overlaps(d_in, d_out, bytes)) return SG_EALIAS;
+  const int passes = (steps + steps_per_pass - 1) / steps_per_pass;
+  if (passes >= 2) {
+    if (!d_work || misaligned(d_work)) return SG_EINVAL;
+    if (overlaps(d_work, d_in, bytes) || overlaps(d_work, d_out, bytes)) return SG_EALIAS;
+  }
+  SG_INJECT();
+  if (steps == 0)
+    return hip_status(hipMemcpyAsync(d_out, d_in, bytes, hipMemcpyDeviceToDevice, a.stream));
+  const uint8_t *src = d_in;
+  for (int k = 1; k <= passes; ++k) {
+    uint8_t *dst = ((passes - k) % 2 == 0) ? d_out : d_work;
+    const int T = k < passes ? steps_per_pass : steps - (passes - 1) * steps_per_pass;
+    const hipError_t e = sg::launch_life_tb_compact(a, T, src, dst);
     if (e != hipSuccess) return hip_status(e);
     src = dst;
   }

@@ -41,6 +41,31 @@ __device__ __forceinline__ void lambda_decode(uint32_t w, int rb, uint32_t &bx,
   by = ly ^ ((1u << rb) - 1u);
 }
 
+// Inverse of lambda_decode: the linear omega of the fractal block (bx, by)
+// (build frame, bx & by == 0).  In the paper frame, bit mu-1 of
+// (lambda_x, lambda_y) is (Delta^x_mu, Delta^y_mu), so the region index at
+// level mu is beta = Delta^x + Delta^y (Eq. 5 read backwards); it is the
+// digit of omega_y (odd mu) or omega_x (even mu) of weight
+// 3^(ceil(mu/2)-1) (Eq. 4), and omega = omega_y * 3^floor(rb/2) + omega_x.
+__device__ __forceinline__ uint32_t lambda_encode(uint32_t bx, uint32_t by, int rb) {
+  const uint32_t ly = by ^ ((1u << rb) - 1u);
+  const int hx = rb >> 1;
+  uint32_t wx = 0, wy = 0, px = 1, py = 1;
+  for (int mu = 1; mu <= rb; ++mu) {
+    const uint32_t beta = ((bx >> (mu - 1)) & 1u) + ((ly >> (mu - 1)) & 1u);
+    if (mu & 1) {
+      wy += beta * py;
+      py *= 3u;
+    } else {
+      wx += beta * px;
+      px *= 3u;
+    }
+  }
+  uint32_t W = 1;
+  for (int j = 0; j < hx; ++j) W *= 3u;
+  return wy * W + wx;
+}
+
 // Lane i receives lane i-1's value (DPP wave_shr:1); lane 0 receives 0.
 __device__ __forceinline__ uint32_t from_prev_lane(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);

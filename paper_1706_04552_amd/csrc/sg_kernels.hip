@@ -533,6 +533,64 @@ hipError_t diffuse_rho(const PassArgs &a, const float *in, float *out, float alp
   });
 }
 
+
+// ------------------------------------------------------------------ intra-block variants
+//
+// The paper's other two intra-block mappings (Section III-D), for the write
+// pass: instead of rho x rho threads with a bounding sub-box test, only the
+// 3^k threads that own a gasket cell of the tile are launched, and each finds
+// its cell either by applying lambda again at thread level ("further
+// unrolling": the tile is itself a gasket of level k) or by reading a table
+// of the 3^k in-tile offsets shared by all tiles ("shared lookup table"),
+// built once per workgroup in LDS.  One byte is stored per thread.
+
+constexpr int pow3c(int k) { return k == 0 ? 1 : 3 * pow3c(k - 1); }
+constexpr int log2c(int v) { return v <= 1 ? 0 : 1 + log2c(v / 2); }
+
+template <int RHO, bool LAMBDA, bool LUT>
+__global__ __launch_bounds__(kWG) void k_write_intra(uint8_t *__restrict__ a, int r, int rb,
+                                                     uint64_t tile_base, uint64_t ntiles,
+                                                     uint32_t value) {
+  constexpr int K = log2c(RHO);
+  constexpr int CELLS = pow3c(K);      // gasket cells per tile
+  constexpr int TPG = kWG / CELLS;     // tiles per workgroup
+  __shared__ uint32_t table[LUT ? CELLS : 1];
+  const int tid = threadIdx.x;
+  if constexpr (LUT) {
+    for (int i = tid; i < CELLS; i += kWG) {
+      uint32_t tx, ty;
+      lambda_decode((uint32_t)i, K, tx, ty);
+      table[i] = tx | (ty << 16);
+    }
+    __syncthreads();
+  }
+  const int slot = tid / CELLS, cell = tid - slot * CELLS;
+  if (slot >= TPG) return;
+  uint32_t bx, by;
+  if (!tile_of<LAMBDA>(tile_base, ntiles, TPG, slot, rb, bx, by)) return;
+  uint32_t tx, ty;
+  if constexpr (LUT) {
+    const uint32_t e = table[cell];
+    tx = e & 0xffffu;
+    ty = e >> 16;
+  } else {
+    lambda_decode((uint32_t)cell, K, tx, ty);
+  }
+  const size_t n = (size_t)1 << r;
+  a[((size_t)by * RHO + ty) * n + (size_t)bx * RHO + tx] = (uint8_t)value;
+}
+
+template <int RHO, bool LUT>
+hipError_t write_intra_rho(const PassArgs &a, uint8_t *d, uint32_t value) {
+  constexpr int TPG = kWG / pow3c(log2c(RHO));
+  return launch_tiles(a.ntiles, TPG, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
+    if (a.lambda)
+      hipLaunchKernelGGL((k_write_intra<RHO, true, LUT>), grid, dim3(kWG), 0, s, d, a.r, a.rb, base, a.ntiles, value);
+    else
+      hipLaunchKernelGGL((k_write_intra<RHO, false, LUT>), grid, dim3(kWG), 0, s, d, a.r, a.rb, base, a.ntiles, value);
+  });
+}
+
 }  // namespace
 
 hipError_t launch_map_lambda(int rb, uint32_t count, uint32_t *d_bxy, hipStream_t s) {
@@ -560,6 +618,18 @@ hipError_t launch_write(const PassArgs &a, uint8_t *d, uint8_t value) {
     case 64: return write_strip<64>(a, d, value);
     case 128: return write_strip<128>(a, d, value);
     case 256: return write_strip<256>(a, d, value);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_write_intra(const PassArgs &a, uint8_t *d, uint8_t value, bool lut) {
+  switch (a.rho) {
+    case 1: return lut ? write_intra_rho<1, true>(a, d, value) : write_intra_rho<1, false>(a, d, value);
+    case 2: return lut ? write_intra_rho<2, true>(a, d, value) : write_intra_rho<2, false>(a, d, value);
+    case 4: return lut ? write_intra_rho<4, true>(a, d, value) : write_intra_rho<4, false>(a, d, value);
+    case 8: return lut ? write_intra_rho<8, true>(a, d, value) : write_intra_rho<8, false>(a, d, value);
+    case 16: return lut ? write_intra_rho<16, true>(a, d, value) : write_intra_rho<16, false>(a, d, value);
+    case 32: return lut ? write_intra_rho<32, true>(a, d, value) : write_intra_rho<32, false>(a, d, value);
     default: return hipErrorInvalidValue;
   }
 }

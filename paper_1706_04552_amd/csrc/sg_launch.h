@@ -25,6 +25,9 @@ struct PassArgs {
 hipError_t launch_map_lambda(int rb, uint32_t count, uint32_t *d_bxy, hipStream_t s);
 hipError_t launch_map_bbox(int rb, uint64_t count, uint8_t *d_mask, hipStream_t s);
 hipError_t launch_write(const PassArgs &a, uint8_t *d, uint8_t value);
+// Write pass with thread-level lambda ("further unrolling", lut = false) or a
+// shared table of in-tile offsets (lut = true); rho <= 32.
+hipError_t launch_write_intra(const PassArgs &a, uint8_t *d, uint8_t value, bool lut);
 hipError_t launch_life(const PassArgs &a, const uint8_t *in, uint8_t *out);
 hipError_t launch_diffuse(const PassArgs &a, const float *in, float *out, float alpha);
 
@@ -33,6 +36,11 @@ hipError_t launch_diffuse(const PassArgs &a, const float *in, float *out, float 
 constexpr int kMaxStepsPerPass = 16;
 bool life_tb_supported(int rho);
 hipError_t launch_life_tb(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
+
+// Block-compacted storage (tiles of side rho in {64, 128, 256}, lambda order).
+hipError_t launch_map_lambda_inverse(int rb, int32_t *d_out, hipStream_t s);
+hipError_t launch_compact_copy(const PassArgs &a, bool pack, const uint8_t *src, uint8_t *dst);
+hipError_t launch_life_tb_compact(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
 
 // Temporally blocked FP32 diffusion: T steps per pass, T in
 // [1, kMaxDiffuseStepsPerPass], for tile side rho = 64.

@@ -122,14 +122,58 @@ __device__ __forceinline__ uint32_t life_rule(const RowSums &u, const RowSums &m
   return eq1 & (bit0 | m.self);
 }
 
-// One tile pass: the rho x rho tile at block (bx, by) of the gasket in `in`
-// (level r) advanced by T generations into `out`, by NT threads.  `lds` holds
-// tb_lds_bytes<RHO>(T) bytes (or more); the caller synchronises the workgroup
-// before reusing it.
-template <int RHO, int NT>
-__device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
-                                        uint8_t *__restrict__ out, int r, uint32_t bx,
-                                        uint32_t by, int T, uint32_t *lds, uint32_t *nseg_p) {
+// Where a tile pass reads and writes cells.
+//
+// DenseMem: the n x n embedding itself.
+struct DenseMem {
+  const uint8_t *in;
+  uint8_t *out;
+  int n;
+  static constexpr bool kCompact = false;
+  __device__ __forceinline__ void prepare(int, uint32_t, uint32_t, int) const {}
+  __device__ __forceinline__ const uint8_t *src(int y, int x) const {
+    return in + (size_t)y * n + x;
+  }
+  __device__ __forceinline__ uint8_t *dst(int y, int x) const { return out + (size_t)y * n + x; }
+};
+
+// CompactMem: only the fractal rho x rho tiles, tile omega stored contiguously
+// (row-major, rows of rho bytes) at omega * rho^2.  A pass reads the 3 x 3
+// tiles around its own, whose omegas (lambda_encode, or -1 off the gasket)
+// are found once per workgroup into `nbr` (9 words of LDS).
+template <int RHO>
+struct CompactMem {
+  const uint8_t *in;
+  uint8_t *out;
+  int32_t *nbr;
+  int bx, by;
+  static constexpr bool kCompact = true;
+  static constexpr int K = rho_log2_const(RHO);
+  __device__ __forceinline__ void prepare(int tid, uint32_t tbx, uint32_t tby, int rb) const {
+    if (tid < 9) {
+      const int x = (int)tbx + tid % 3 - 1, y = (int)tby + tid / 3 - 1;
+      const int nb = 1 << rb;
+      int32_t w = -1;
+      if (x >= 0 && y >= 0 && x < nb && y < nb && (x & y) == 0)
+        w = (int32_t)lambda_encode((uint32_t)x, (uint32_t)y, rb);
+      nbr[tid] = w;
+    }
+  }
+  __device__ __forceinline__ size_t tile_off(int y, int x) const {
+    const int dy = (y >> K) - by + 1, dx = (x >> K) - bx + 1;
+    return (size_t)nbr[dy * 3 + dx] * (RHO * RHO) + (size_t)(y & (RHO - 1)) * RHO + (x & (RHO - 1));
+  }
+  __device__ __forceinline__ const uint8_t *src(int y, int x) const { return in + tile_off(y, x); }
+  __device__ __forceinline__ uint8_t *dst(int y, int x) const { return out + tile_off(y, x); }
+};
+
+// One tile pass: the rho x rho tile at block (bx, by) of the gasket of level
+// r advanced by T generations from mem.src to mem.dst, by NT threads.  `lds`
+// holds tb_lds_bytes<RHO>(T) bytes (or more); the caller synchronises the
+// workgroup before reusing it.
+template <int RHO, int NT, class Mem>
+__device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint32_t by, int T,
+                                        uint32_t *lds, uint32_t *nseg_p) {
   uint32_t &nseg = *nseg_p;
   constexpr int kTbThreads = NT;
   // Region columns [X0-16, X0+RHO+16): the tile plus one 16-cell chunk each
@@ -157,6 +201,7 @@ __device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
   uint32_t *rowpat = plane1 + PR * PW;  // RP: gasket pattern of each region row (both halves)
   uint32_t *segs = rowpat + RP;         // W * NB: listed segments
 
+  mem.prepare(tid, bx, by, r - rho_log2_const(RHO));
   for (int i = tid; i < 2 * PR * PW; i += kTbThreads) lds[i] = 0u;
   for (int i = tid; i < RP; i += kTbThreads) {
     const int y = yr0 + i;
@@ -180,7 +225,7 @@ __device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
         const int i = e / CH, j = e - (e / CH) * CH;
         const int y = yr0 + i, x = X0 - 16 + 16 * j;
         if (y >= 0 && y < n && x >= 0 && x < n && (x & y) == 0) {
-          v[q] = *reinterpret_cast<const uint4 *>(in + (size_t)y * n + x);
+          v[q] = *reinterpret_cast<const uint4 *>(mem.src(y, x));
           slot[q] = ((i + 1) * PW + ((j >> 1) + 1)) * 2 + (j & 1);
         }
       }
@@ -268,10 +313,12 @@ __device__ __forceinline__ void tb_tile(const uint8_t *__restrict__ in,
   for (int e = tid; e < RHO * TC; e += kTbThreads) {
     const int ty = e / TC, j = e - (e / TC) * TC;
     const int y = Y0 + ty, x = X0 + 16 * j;
-    if (((x & ~63) & y) != 0) continue;
+    // the embedding keeps granules without a gasket cell untouched; a compact
+    // tile is rewritten whole
+    if (!Mem::kCompact && ((x & ~63) & y) != 0) continue;
     const int w = (j + 1) >> 1, half = (j + 1) & 1;  // region chunk j + 1
     const uint32_t bits = fin[((T + ty + 1) * PW + (w + 1)) * 2 + half];
-    *reinterpret_cast<uint4 *>(out + (size_t)y * n + x) = unpack16(bits);
+    *reinterpret_cast<uint4 *>(mem.dst(y, x)) = unpack16(bits);
   }
 }
 
@@ -293,7 +340,24 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__
     bx = (uint32_t)(t & ((1ull << rb) - 1ull));
     if ((bx & by) != 0u) return;
   }
-  tb_tile<RHO, tb_threads<RHO>()>(in, out, r, bx, by, T, lds, &nseg);
+  tb_tile<RHO, tb_threads<RHO>()>(DenseMem{in, out, 1 << r}, r, bx, by, T, lds, &nseg);
+}
+
+// One workgroup per tile of a gasket in block-compacted storage (lambda
+// order): tile omega is the workgroup's omega.
+template <int RHO>
+__global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb_compact(
+    const uint8_t *__restrict__ in, uint8_t *__restrict__ out, int r, int rb,
+    uint64_t tile_base, uint64_t ntiles, int T) {
+  extern __shared__ uint32_t lds[];
+  __shared__ uint32_t nseg;
+  __shared__ int32_t nbr[9];
+  const uint64_t t = tile_base + blockIdx.x;
+  if (t >= ntiles) return;
+  uint32_t bx, by;
+  lambda_decode((uint32_t)t, rb, bx, by);
+  const CompactMem<RHO> mem{in, out, nbr, (int)bx, (int)by};
+  tb_tile<RHO, tb_threads<RHO>()>(mem, r, bx, by, T, lds, &nseg);
 }
 
 // Many gaskets in one persistent launch: workgroups stride over the global
@@ -317,11 +381,13 @@ __global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restric
     uint32_t bx, by;
     lambda_decode((uint32_t)(g - it.tile_begin), it.r - it.k, bx, by);
     if (it.k == 6) {
-      tb_tile<64, NT>(it.src, it.dst, it.r, bx, by, it.steps, lds, &nseg);
+      tb_tile<64, NT>(DenseMem{it.src, it.dst, 1 << it.r}, it.r, bx, by, it.steps, lds, &nseg);
     } else if (MAXRHO >= 128 && it.k == 7) {
-      tb_tile<(MAXRHO >= 128 ? 128 : 64), NT>(it.src, it.dst, it.r, bx, by, it.steps, lds, &nseg);
+      tb_tile<(MAXRHO >= 128 ? 128 : 64), NT>(DenseMem{it.src, it.dst, 1 << it.r}, it.r, bx, by,
+                                              it.steps, lds, &nseg);
     } else if (MAXRHO >= 256 && it.k == 8) {
-      tb_tile<(MAXRHO >= 256 ? 256 : 64), NT>(it.src, it.dst, it.r, bx, by, it.steps, lds, &nseg);
+      tb_tile<(MAXRHO >= 256 ? 256 : 64), NT>(DenseMem{it.src, it.dst, 1 << it.r}, it.r, bx, by,
+                                              it.steps, lds, &nseg);
     }
     __syncthreads();  // the next tile reuses the LDS planes
   }
@@ -346,6 +412,20 @@ hipError_t life_tb_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out
     else
       hipLaunchKernelGGL((k_life_tb<RHO, false>), dim3((unsigned)g), dim3(tb_threads<RHO>()), lds,
                          a.stream, in, out, a.r, a.rb, g0, a.ntiles, T);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int RHO>
+hipError_t life_tb_compact_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out) {
+  const size_t lds = tb_lds_bytes<RHO>(T);
+  const uint64_t per_launch = 1ull << 22;
+  for (uint64_t g0 = 0; g0 < a.ntiles; g0 += per_launch) {
+    const uint64_t g = a.ntiles - g0 < per_launch ? a.ntiles - g0 : per_launch;
+    hipLaunchKernelGGL((k_life_tb_compact<RHO>), dim3((unsigned)g), dim3(tb_threads<RHO>()), lds,
+                       a.stream, in, out, a.r, a.rb, g0, a.ntiles, T);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -379,6 +459,16 @@ hipError_t launch_life_tb_batch(int max_rho, int threads, const BatchItem *d_ite
                           : life_tb_batch_rho<128, 256>(d_items, count, total_tiles, max_steps, groups, stream);
     case 256: return t512 ? life_tb_batch_rho<256, 512>(d_items, count, total_tiles, max_steps, groups, stream)
                           : life_tb_batch_rho<256, 256>(d_items, count, total_tiles, max_steps, groups, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_life_tb_compact(const PassArgs &a, int T, const uint8_t *in, uint8_t *out) {
+  if (T < 1 || T > kMaxStepsPerPass) return hipErrorInvalidValue;
+  switch (a.rho) {
+    case 64: return life_tb_compact_rho<64>(a, T, in, out);
+    case 128: return life_tb_compact_rho<128>(a, T, in, out);
+    case 256: return life_tb_compact_rho<256>(a, T, in, out);
     default: return hipErrorInvalidValue;
   }
 }

@@ -16,6 +16,8 @@ from . import build as _build
 
 SG_OK, SG_EINVAL, SG_EALIAS, SG_EHIP, SG_ENOMEM = 0, -1, -2, -3, -4
 SG_MAP_LAMBDA, SG_MAP_BBOX = 0, 1
+SG_INTRA_SUBBOX, SG_INTRA_UNROLL, SG_INTRA_LUT = 0, 1, 2
+INTRA = {"subbox": SG_INTRA_SUBBOX, "unroll": SG_INTRA_UNROLL, "lut": SG_INTRA_LUT}
 SG_MAX_R, SG_MAX_RHO = 20, 256
 MAPS = {"lambda": SG_MAP_LAMBDA, "bbox": SG_MAP_BBOX}
 
@@ -51,6 +53,8 @@ _SIGNATURES = {
     "sg_map_bbox": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "sg_write_pass": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                      ctypes.c_uint8, ctypes.c_void_p]),
+    "sg_write_pass_intra": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_uint8, ctypes.c_void_p]),
     "sg_ca_step": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p]),
     "sg_ca_steps": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -61,6 +65,16 @@ _SIGNATURES = {
     "sg_diffuse_steps": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p]),
+    "sg_map_lambda_inverse": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "sg_compact_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _u64p]),
+    "sg_compact_pack": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "sg_compact_unpack": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_ca_steps_compact": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
     "sg_tune_default": (ctypes.c_int, [_tunep]),
     "sg_batch_create": (ctypes.c_int, [ctypes.POINTER(sg_gasket), ctypes.c_int, _tunep,
                                        ctypes.POINTER(_vp)]),
@@ -190,6 +204,16 @@ def sg_write_pass(map_kind, r: int, rho: int, d_a: torch.Tensor, value: int = 1,
     return d_a
 
 
+def sg_write_pass_intra(map_kind, intra, r: int, rho: int, d_a: torch.Tensor, value: int = 1,
+                        stream=None) -> torch.Tensor:
+    """Write pass with intra-block mapping "subbox", "unroll" or "lut"."""
+    p = _dev(d_a, torch.uint8, _n2(r), "d_a")
+    k = INTRA[intra] if isinstance(intra, str) else int(intra)
+    _check(load().sg_write_pass_intra(_map(map_kind), k, r, rho, p, value, _stream(stream)),
+           "sg_write_pass_intra")
+    return d_a
+
+
 def sg_ca_step(map_kind, r: int, rho: int, d_in: torch.Tensor, d_out: torch.Tensor,
                stream=None) -> torch.Tensor:
     n2 = _n2(r)
@@ -232,4 +256,46 @@ def sg_diffuse_steps(map_kind, r: int, rho: int, steps: int, d_in: torch.Tensor,
     pw = _dev(d_work, torch.float32, n2, "d_work") if d_work is not None else None
     _check(load().sg_diffuse_steps(_map(map_kind), r, rho, steps, steps_per_pass, pi, po, pw,
                                    alpha, _stream(stream)), "sg_diffuse_steps")
+    return d_out
+
+
+def sg_map_lambda_inverse(r: int, rho: int, d_omega: torch.Tensor, stream=None) -> torch.Tensor:
+    """d_omega (int32, n_b*n_b): omega of each block, -1 off the gasket."""
+    nb = (1 << r) // rho if rho > 0 else 0
+    p = _dev(d_omega, torch.int32, nb * nb, "d_omega")
+    _check(load().sg_map_lambda_inverse(r, rho, p, _stream(stream)), "sg_map_lambda_inverse")
+    return d_omega
+
+
+def sg_compact_bytes(r: int, rho: int) -> int:
+    b = ctypes.c_uint64()
+    _check(load().sg_compact_bytes(r, rho, ctypes.byref(b)), "sg_compact_bytes")
+    return b.value
+
+
+def sg_compact_pack(r: int, rho: int, d_dense: torch.Tensor, d_compact: torch.Tensor,
+                    stream=None) -> torch.Tensor:
+    pd = _dev(d_dense, torch.uint8, _n2(r), "d_dense")
+    pc = _dev(d_compact, torch.uint8, sg_compact_bytes(r, rho), "d_compact")
+    _check(load().sg_compact_pack(r, rho, pd, pc, _stream(stream)), "sg_compact_pack")
+    return d_compact
+
+
+def sg_compact_unpack(r: int, rho: int, d_compact: torch.Tensor, d_dense: torch.Tensor,
+                      stream=None) -> torch.Tensor:
+    pc = _dev(d_compact, torch.uint8, sg_compact_bytes(r, rho), "d_compact")
+    pd = _dev(d_dense, torch.uint8, _n2(r), "d_dense")
+    _check(load().sg_compact_unpack(r, rho, pc, pd, _stream(stream)), "sg_compact_unpack")
+    return d_dense
+
+
+def sg_ca_steps_compact(r: int, rho: int, steps: int, d_in: torch.Tensor, d_out: torch.Tensor,
+                        d_work: Optional[torch.Tensor] = None, steps_per_pass: int = 0,
+                        stream=None) -> torch.Tensor:
+    size = sg_compact_bytes(r, rho)
+    pi = _dev(d_in, torch.uint8, size, "d_in")
+    po = _dev(d_out, torch.uint8, size, "d_out")
+    pw = _dev(d_work, torch.uint8, size, "d_work") if d_work is not None else None
+    _check(load().sg_ca_steps_compact(r, rho, steps, steps_per_pass, pi, po, pw, _stream(stream)),
+           "sg_ca_steps_compact")
     return d_out

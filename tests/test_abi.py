@@ -228,3 +228,52 @@ def test_diffuse_steps_validation(lib):
     assert lib.sg_diffuse_steps(0, r, 64, 10, 4, a, b, None, 0.2, None) == sg.SG_EINVAL
     assert lib.sg_diffuse_steps(0, r, 64, 10, 4, a, ctypes.c_void_p(0x100000 + 4096), w, 0.2, None) == sg.SG_EALIAS
     assert lib.sg_diffuse_steps(0, r, 64, 10, 4, a, b, ctypes.c_void_p(0x7000000000 + 16), 0.2, None) == sg.SG_EALIAS
+
+
+def test_write_pass_intra_validation(lib):
+    from paper_1706_04552_amd import sg
+    a = ctypes.c_void_p(0x100000)
+    assert lib.sg_write_pass_intra(0, 3, 8, 16, a, 1, None) == sg.SG_EINVAL
+    assert lib.sg_write_pass_intra(0, -1, 8, 16, a, 1, None) == sg.SG_EINVAL
+    assert lib.sg_write_pass_intra(0, sg.SG_INTRA_UNROLL, 8, 64, a, 1, None) == sg.SG_EINVAL
+    assert lib.sg_write_pass_intra(1, sg.SG_INTRA_LUT, 8, 128, a, 1, None) == sg.SG_EINVAL
+    assert lib.sg_write_pass_intra(2, sg.SG_INTRA_LUT, 8, 16, a, 1, None) == sg.SG_EINVAL
+    assert lib.sg_write_pass_intra(0, sg.SG_INTRA_LUT, 8, 16, None, 1, None) == sg.SG_EINVAL
+
+
+def test_compact_storage_validation(lib):
+    from paper_1706_04552_amd import sg
+    b64 = ctypes.c_uint64()
+    assert lib.sg_compact_bytes(10, 64, ctypes.byref(b64)) == sg.SG_OK
+    assert b64.value == 3 ** 4 * 64 * 64
+    assert lib.sg_compact_bytes(16, 256, ctypes.byref(b64)) == sg.SG_OK
+    assert b64.value == 3 ** 8 * 256 * 256
+    # only the temporally blocked tile sides, and a gasket at least a tile wide
+    for r, rho in ((10, 32), (10, 16), (5, 64), (10, 512), (21, 256)):
+        assert lib.sg_compact_bytes(r, rho, ctypes.byref(b64)) == sg.SG_EINVAL
+    assert lib.sg_compact_bytes(10, 64, None) == sg.SG_EINVAL
+    r, rho = 10, 64  # dense 1 MiB, compact 324 KiB
+    dense, comp = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x7000000000)
+    assert lib.sg_compact_pack(r, 32, dense, comp, None) == sg.SG_EINVAL
+    assert lib.sg_compact_pack(r, rho, None, comp, None) == sg.SG_EINVAL
+    assert lib.sg_compact_unpack(r, rho, comp, None, None) == sg.SG_EINVAL
+    assert lib.sg_compact_pack(r, rho, ctypes.c_void_p(0x100008), comp, None) == sg.SG_EINVAL
+    # the dense array reaches 1 MiB past its start, the compact one 324 KiB
+    assert lib.sg_compact_pack(r, rho, dense, ctypes.c_void_p(0x100000 + (1 << 20) - 16),
+                               None) == sg.SG_EALIAS
+    assert lib.sg_compact_unpack(r, rho, ctypes.c_void_p(0x100000 - 81 * 4096 + 16), dense,
+                                 None) == sg.SG_EALIAS
+    a, b, w = (ctypes.c_void_p(0x100000), ctypes.c_void_p(0x7000000000),
+               ctypes.c_void_p(0x7100000000))
+    assert lib.sg_ca_steps_compact(r, rho, 10, 17, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps_compact(r, 32, 10, 4, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps_compact(r, rho, -1, 4, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps_compact(r, rho, 17, 16, a, b, None, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps_compact(r, rho, 17, 16, a, ctypes.c_void_p(0x100000 + 81 * 4096 - 16),
+                                   w, None) == sg.SG_EALIAS
+    assert lib.sg_ca_steps_compact(r, rho, 17, 16, a, b, ctypes.c_void_p(0x7000000000 + 16),
+                                   None) == sg.SG_EALIAS
+    # the inverse map: omega must fit an int32, the output array 4-byte aligned
+    assert lib.sg_map_lambda_inverse(r, rho, None, None) == sg.SG_EINVAL
+    assert lib.sg_map_lambda_inverse(r, rho, ctypes.c_void_p(0x100002), None) == sg.SG_EINVAL
+    assert lib.sg_map_lambda_inverse(20, 1, ctypes.c_void_p(0x100000), None) == sg.SG_EINVAL

@@ -122,6 +122,17 @@ def test_write_pass_exact(map_kind, r, rho):
         assert np.array_equal(a.cpu().numpy(), O.write_pass(r, v))
 
 
+@pytest.mark.parametrize("intra", ["unroll", "lut", "subbox"])
+@pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
+@pytest.mark.parametrize("r,rho", cases([0, 1, 3, 6, 9, 11], [1, 2, 4, 8, 16, 32]))
+def test_write_pass_intra_block_variants(intra, map_kind, r, rho):
+    note(f"write_pass_intra {intra} {map_kind} r={r} rho={rho}")
+    n = 1 << r
+    a = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+    sg.sg_write_pass_intra(map_kind, intra, r, rho, a, 9)
+    assert np.array_equal(a.cpu().numpy(), O.write_pass(r, 9))
+
+
 # ------------------------------------------------------------------ life
 
 @pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
@@ -311,3 +322,76 @@ def test_diffuse_steps_full_size_sampled():
         gots.append(got[y0:y0 + 8, x0:x0 + 8])
     max_abs, scale, rel_l2 = diff_errors(np.concatenate(gots), np.concatenate(refs))
     assert max_abs <= DIFF_RTOL * scale and rel_l2 <= DIFF_RTOL
+
+
+# ------------------------------------------------------------------ block-compacted storage
+
+def _compact_reference(r, rho, a0):
+    """Tiles of the embedding gathered in omega order (the oracle's lambda table)."""
+    tab = O.map_lambda(r - (rho.bit_length() - 1))
+    tiles = [a0[by * rho:(by + 1) * rho, bx * rho:(bx + 1) * rho] for bx, by in tab]
+    return np.stack(tiles).reshape(-1)
+
+
+@pytest.mark.parametrize("r,rho", [(1, 1), (4, 2), (6, 1), (8, 16), (10, 64), (12, 4), (16, 256)])
+def test_map_lambda_inverse_exact(r, rho):
+    note(f"map_lambda_inverse r={r} rho={rho}")
+    rb = r - (rho.bit_length() - 1)
+    nb = 1 << rb
+    tab = O.map_lambda(rb)
+    ref = np.full((nb, nb), -1, dtype=np.int32)
+    ref[tab[:, 1], tab[:, 0]] = np.arange(len(tab), dtype=np.int32)
+    got = torch.full((nb * nb,), -7, dtype=torch.int32, device="cuda")
+    sg.sg_map_lambda_inverse(r, rho, got)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().reshape(nb, nb), ref)
+
+
+@pytest.mark.parametrize("r,rho", [(6, 64), (8, 64), (9, 128), (10, 256), (11, 64)])
+def test_compact_round_trip(r, rho):
+    note(f"compact pack/unpack r={r} rho={rho}")
+    a0 = inputs.bernoulli_state(r, 0.5, 77 + r)
+    comp = torch.full((sg.sg_compact_bytes(r, rho),), 0xAB, dtype=torch.uint8, device="cuda")
+    sg.sg_compact_pack(r, rho, dev(a0), comp)
+    back = torch.zeros((1 << r, 1 << r), dtype=torch.uint8, device="cuda")
+    sg.sg_compact_unpack(r, rho, comp, back)
+    torch.cuda.synchronize()
+    assert np.array_equal(comp.cpu().numpy(), _compact_reference(r, rho, a0))
+    assert np.array_equal(back.cpu().numpy(), a0)
+
+
+def gpu_ca_steps_compact(r, rho, a0, steps, spp):
+    size = sg.sg_compact_bytes(r, rho)
+    cin = torch.empty(size, dtype=torch.uint8, device="cuda")
+    sg.sg_compact_pack(r, rho, dev(a0), cin)
+    keep = cin.clone()
+    # garbage in the output and work buffers: every pass rewrites whole tiles
+    out = torch.full((size,), 0x5A, dtype=torch.uint8, device="cuda")
+    work = torch.full((size,), 0xC3, dtype=torch.uint8, device="cuda")
+    sg.sg_ca_steps_compact(r, rho, steps, cin, out, work, steps_per_pass=spp)
+    dense = torch.zeros((1 << r, 1 << r), dtype=torch.uint8, device="cuda")
+    sg.sg_compact_unpack(r, rho, out, dense)
+    torch.cuda.synchronize()
+    assert torch.equal(cin, keep)  # the input is read only
+    return dense
+
+
+@pytest.mark.parametrize("r,rho,steps,spp", [
+    (6, 64, 1, 16), (6, 64, 16, 16), (7, 64, 23, 8), (7, 128, 5, 5), (8, 256, 40, 16),
+    (9, 64, 33, 16), (10, 128, 50, 16), (10, 256, 17, 16), (10, 64, 12, 1), (11, 128, 31, 7),
+    (10, 256, 0, 16), (12, 256, 100, 16), (12, 64, 100, 16)])
+def test_ca_steps_compact_exact(r, rho, steps, spp):
+    note(f"ca_steps_compact r={r} rho={rho} steps={steps} per_pass={spp}")
+    a0 = inputs.bernoulli_state(r, 0.5, 1706 + 3 * r)
+    got = gpu_ca_steps_compact(r, rho, a0, steps, spp).cpu().numpy()
+    ref = a0 if steps == 0 else O.life_steps(r, a0, steps)
+    assert np.array_equal(got, ref)
+
+
+def test_ca_steps_compact_full_size_equals_embedding():
+    r, rho, steps = 16, 256, 100
+    note(f"ca_steps_compact full-size r={r} rho={rho} {steps} steps")
+    a0 = inputs.bernoulli_state(r, 0.5, 1706)
+    comp = gpu_ca_steps_compact(r, rho, a0, steps, 16)
+    emb = gpu_ca_steps("lambda", r, rho, a0, steps, 16)
+    assert torch.equal(comp, emb)
