@@ -213,7 +213,8 @@ def bench_batched(torch, sg, inputs, count, steps, runs):
 
     def one_at_a_time():
         for g in gs:
-            sg.sg_ca_steps("lambda", g.r, 64, steps, g.inp, g.out, g.work, steps_per_pass=16)
+            sg.sg_ca_steps("lambda", g.r, min(256, 1 << g.r), steps, g.inp, g.out, g.work,
+                           steps_per_pass=0)
     ms = time_region(torch, one_at_a_time, 1, 1)
     out["one_at_a_time_ms"] = round(ms, 3)
     out["one_at_a_time_cells_per_s"] = cell_steps / (ms * 1e-3)
@@ -288,7 +289,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--rho", type=int, nargs="*", default=list(RHOS))
-    ap.add_argument("--per-pass", type=int, nargs="*", default=[4, 8, 16],
+    ap.add_argument("--per-pass", type=int, nargs="*", default=[8, 16, 32],
                     help="generations per pass for the temporally blocked step")
     ap.add_argument("--skip-single", action="store_true",
                     help="skip the one-launch-per-generation sweep")

@@ -142,8 +142,8 @@ SG_API int sg_ca_step(int map, int r, int rho, const uint8_t *d_in,
  * from HBM once, runs the generations on chip and writes the tile once
  * (temporal blocking), so HBM traffic per generation falls by that factor.
  * The result is identical to `steps` calls of sg_ca_step.
- *   steps_per_pass: 1 (one launch per generation, any rho), 2..16 (rho in
- *     {64, 128, 256}), or 0 for the library's choice (16 where supported,
+ *   steps_per_pass: 1 (one launch per generation, any rho), 2..32 (rho in
+ *     {64, 128, 256}), or 0 for the library's choice (32 where supported,
  *     else 1).
  *   d_in: read only.  d_out: receives the state after `steps` generations.
  *   d_work: a third n * n buffer used when more than one pass runs (may be
@@ -202,7 +202,7 @@ SG_API int sg_compact_unpack(int r, int rho, const uint8_t *d_compact, uint8_t *
                              void *stream);
 
 /* sg_ca_steps on compact states (lambda map): `steps` life generations
- * from d_in into d_out, up to `steps_per_pass` (1..16, 0 = 16) per pass;
+ * from d_in into d_out, up to `steps_per_pass` (1..32, 0 = 32) per pass;
  * every pass rewrites its output tiles whole, so d_out and d_work need no
  * zeroing.  All three: compact-sized, 16-byte aligned, non-overlapping.
  * Errors: SG_EINVAL, SG_EALIAS, SG_EHIP. */
@@ -220,7 +220,7 @@ SG_API int sg_ca_steps_compact(int r, int rho, int steps, int steps_per_pass,
 /* Launch shape of a batched pass.
  *   rho:            largest lambda tile side, 64, 128 or 256; a gasket of
  *                   side n < rho uses tiles of side n (gaskets need n >= 64)
- *   steps_per_pass: generations per pass, 1..16
+ *   steps_per_pass: generations per pass, 1..32
  *   groups_per_cu:  persistent workgroups per compute unit, 1..64, or 0 for
  *                   one workgroup per tile
  *   threads:        threads per workgroup, 256 or 512 */
@@ -254,7 +254,7 @@ typedef struct sg_pass_item {
 typedef struct sg_batch sg_batch;       /* planned batch with a captured hipGraph */
 typedef struct sg_pass_ctx sg_pass_ctx; /* device item table for repeated passes */
 
-/* Host only.  A valid default shape (rho 64, 16 generations per pass, one
+/* Host only.  A valid default shape (rho 64, 32 generations per pass, one
  * workgroup per tile, 256 threads). */
 SG_API int sg_tune_default(sg_tune *tune);
 

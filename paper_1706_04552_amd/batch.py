@@ -38,7 +38,7 @@ def _gasket_array(gaskets: Sequence[Gasket]):
     return arr
 
 
-def make_tune(rho: int = 64, steps_per_pass: int = 16, groups_per_cu: int = 0,
+def make_tune(rho: int = 64, steps_per_pass: int = 32, groups_per_cu: int = 0,
               threads: int = 256) -> "sg.sg_tune":
     return sg.sg_tune(rho, steps_per_pass, groups_per_cu, threads)
 

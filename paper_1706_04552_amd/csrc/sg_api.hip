@@ -164,7 +164,7 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
   if (st != SG_OK) return st;
   if (steps < 0 || steps_per_pass < 0 || steps_per_pass > sg::kMaxStepsPerPass) return SG_EINVAL;
   const bool tb_ok = sg::life_tb_supported(rho);
-  if (steps_per_pass == 0) steps_per_pass = tb_ok ? sg::kMaxStepsPerPass : 1;
+  if (steps_per_pass == 0) steps_per_pass = tb_ok ? sg::kDefaultStepsPerPass : 1;
   if (steps_per_pass > 1 && !tb_ok) return SG_EINVAL;
   if (!d_in || !d_out || misaligned(d_in) || misaligned(d_out)) return SG_EINVAL;
   const size_t bytes = ((size_t)1 << r) * ((size_t)1 << r);
@@ -276,7 +276,7 @@ SG_API int sg_ca_steps_compact(int r, int rho, int steps, int steps_per_pass,
   if (!sg::life_tb_supported(rho) || steps < 0 || steps_per_pass < 0 ||
       steps_per_pass > sg::kMaxStepsPerPass)
     return SG_EINVAL;
-  if (steps_per_pass == 0) steps_per_pass = sg::kMaxStepsPerPass;
+  if (steps_per_pass == 0) steps_per_pass = sg::kDefaultStepsPerPass;
   if (!d_in || !d_out || misaligned(d_in) || misaligned(d_out)) return SG_EINVAL;
   const size_t bytes = (size_t)pow3(a.rb) * (size_t)rho * (size_t)rho;
   if (overlaps(d_in, d_out, bytes)) return SG_EALIAS;

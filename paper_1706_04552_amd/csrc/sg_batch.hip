@@ -204,7 +204,7 @@ extern "C" {
 SG_API int sg_tune_default(sg_tune *t) {
   if (!t) return SG_EINVAL;
   t->rho = 64;
-  t->steps_per_pass = sg::kMaxStepsPerPass;
+  t->steps_per_pass = sg::kDefaultStepsPerPass;
   t->groups_per_cu = 0;
   t->threads = 256;
   return SG_OK;
@@ -283,7 +283,7 @@ SG_API int sg_batch_autotune(const sg_gasket *gaskets, int count, sg_tune *best,
   }
   float best_t = -1.0f;
   int st_any = SG_EINVAL;
-  const int rhos[] = {64, 128, 256}, spps[] = {8, 16}, gpcs[] = {0, 2, 4, 8}, thr[] = {256, 512};
+  const int rhos[] = {64, 128, 256}, spps[] = {8, 16, 32}, gpcs[] = {0, 2, 4, 8}, thr[] = {256, 512};
   for (int rho : rhos) {
     for (int spp : spps)
       for (int gpc : gpcs)

@@ -33,7 +33,8 @@ hipError_t launch_diffuse(const PassArgs &a, const float *in, float *out, float 
 
 // Temporally blocked life: T generations per pass, T in [1, kMaxStepsPerPass],
 // for tile sides rho in {64, 128, 256}.
-constexpr int kMaxStepsPerPass = 16;
+constexpr int kMaxStepsPerPass = 32;
+constexpr int kDefaultStepsPerPass = 32;  // what steps_per_pass = 0 selects
 bool life_tb_supported(int rho);
 hipError_t launch_life_tb(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
 

@@ -1,13 +1,14 @@
 // Temporally blocked B3/S23 life on the gasket (gfx950).
 //
 // One workgroup owns one rho x rho tile of the map (lambda or bounding box)
-// and advances it by T generations per pass (T <= 16), so HBM is read and
+// and advances it by T generations per pass (T <= 32), so HBM is read and
 // written once per T steps instead of once per step.
 //
-//  1. Load the tile plus a halo of T rows above/below and one 16-byte chunk
-//     left/right (T <= 16 cells) from HBM, skipping chunks with no gasket
+//  1. Load the tile plus a halo of T rows above/below and T cells left/right
+//     (one or two 16-byte chunks) from HBM, skipping chunks with no gasket
 //     cell, and bit-pack each 16-byte chunk of 0/1 bytes into 16 bits of an
-//     LDS plane (one bit per cell, 32 cells per word).
+//     LDS plane (one bit per cell, 32 cells per word, the words aligned to
+//     multiples of 32 cells).
 //  2. List, once, the vertical segments (one 32-cell word column, kSegRows
 //     rows) that hold a gasket cell (wavefront ballot + prefix count), and
 //     the gasket pattern of every region row (bounding sub-box test
@@ -15,12 +16,13 @@
 //  3. T times: each listed segment walks down its rows keeping the
 //     horizontal 3-cell sums of the rows above, at and below in registers
 //     (bit-sliced: lsb and carry planes), so every row's sums are formed once
-//     and used for three output rows; the count of the 8 neighbours and the
-//     B3/S23 rule are evaluated on the bit planes and masked to the gasket.
+//     and used for three output rows; the 3 x 3 sum and the B3/S23 rule are
+//     evaluated on the bit planes, one v_bitop3 per three-input function,
+//     and masked to the gasket.
 //     Planes ping-pong with a barrier between generations.  Cells outside the
 //     region are taken as dead; the wrong values this makes at the region's
 //     cut edges move inward one cell per generation and never reach the tile
-//     in T <= 16.
+//     in T generations.
 //  4. Unpack the tile and store every 64-byte granule that holds a gasket
 //     cell in full.
 #include "sg_device.h"
@@ -85,41 +87,49 @@ __device__ __forceinline__ uint32_t word_pattern(uint32_t y) {
   return m;
 }
 
-// Horizontal sums of a row word with its west and east neighbours, as bit
-// planes: (s, c) with value s + 2c.  Three cells (west, centre, east) for the
-// rows above and below, two (west, east) for the row itself.
+// Three-input bitwise functions as one v_bitop3 each.  The 8-bit truth table
+// of f(a, b, c) is f applied to the constant columns kA, kB, kC (bit
+// 4a + 2b + c of the table is f(a, b, c)).
+constexpr uint32_t kA = 0xF0u, kB = 0xCCu, kC = 0xAAu;
+constexpr uint32_t kXor3 = kA ^ kB ^ kC;
+constexpr uint32_t kMaj3 = (kA & kB) | (kA & kC) | (kB & kC);
+template <uint32_t F>
+__device__ __forceinline__ uint32_t bop3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, F & 0xFFu);
+}
+
+// Horizontal 3-cell sums (west + centre + east) of a row word, as bit planes
+// (h0 + 2 * h1), from the word and its west and east neighbour words.
 struct RowSums {
-  uint32_t s3, c3;  // west + centre + east
-  uint32_t s2, c2;  // west + east
-  uint32_t self;    // the centre cells
+  uint32_t h0, h1;
+  uint32_t self;  // the centre cells
 };
 
 __device__ __forceinline__ RowSums row_sums(uint32_t left, uint32_t mid, uint32_t right) {
   const uint32_t w = __builtin_amdgcn_alignbit(mid, left, 31);  // bit i <- cell x-1
   const uint32_t e = __builtin_amdgcn_alignbit(right, mid, 1);  // bit i <- cell x+1
-  RowSums h;
-  h.s3 = w ^ mid ^ e;
-  h.c3 = (w & mid) | (w & e) | (mid & e);
-  h.s2 = w ^ e;
-  h.c2 = w & e;
-  h.self = mid;
-  return h;
+  return RowSums{bop3<kXor3>(w, mid, e), bop3<kMaj3>(w, mid, e), mid};
 }
 
 // B3/S23 for 32 cells from the sums of the rows above (u), at (m) and below
-// (d).  The neighbour count is bit0 + 2 * (u.c3 + m.c2 + d.c3 + k), where
-// bit0 and k are the sum and carry of the three lsb planes; it is 2 or 3 iff
-// exactly one of those four carries is set.
+// (d), masked to the gasket cells `mask0 & mask1`.  With S the 3 x 3 sum
+// (centre included) a cell lives next iff S == 3, or S == 4 and it is alive.
+// Writing S = s0 + 2 (a + k) + 4 b, where (s0, k) are the sum and carry of
+// the three lsb planes and (a, b) those of the three msb planes:
+//   S == 3  iff  s0 and not b and (a xor k),
+//   S == 4  iff  not s0 and ((not b, a, k) or (b, not a, not k)).
 __device__ __forceinline__ uint32_t life_rule(const RowSums &u, const RowSums &m,
-                                              const RowSums &d) {
-  const uint32_t bit0 = u.s3 ^ m.s2 ^ d.s3;
-  const uint32_t k = (u.s3 & m.s2) | (u.s3 & d.s3) | (m.s2 & d.s3);
-  const uint32_t x3 = u.c3 ^ m.c2 ^ d.c3;
-  const uint32_t m3 = (u.c3 & m.c2) | (u.c3 & d.c3) | (m.c2 & d.c3);
-  const uint32_t o3 = u.c3 | m.c2 | d.c3;
-  const uint32_t e3 = x3 & ~m3;                // exactly one of the three carries
-  const uint32_t eq1 = (e3 & ~k) | (~o3 & k);  // exactly one of the four
-  return eq1 & (bit0 | m.self);
+                                              const RowSums &d, uint32_t mask0,
+                                              uint32_t mask1) {
+  const uint32_t s0 = bop3<kXor3>(u.h0, m.h0, d.h0);
+  const uint32_t k = bop3<kMaj3>(u.h0, m.h0, d.h0);
+  const uint32_t a = bop3<kXor3>(u.h1, m.h1, d.h1);
+  const uint32_t b = bop3<kMaj3>(u.h1, m.h1, d.h1);
+  const uint32_t e3 = bop3<~kA & (kB ^ kC)>(b, a, k);                         // rest of S == 3
+  const uint32_t e4 = bop3<(~kA & kB & kC) | (kA & ~kB & ~kC)>(b, a, k);      // rest of S == 4
+  const uint32_t f = bop3<(kA & kB) | (~kA & kC)>(s0, e3, e4);                // s0 ? e3 : e4
+  const uint32_t g = bop3<kA & (kB | kC)>(f, s0, m.self);                     // f & (s0 | self)
+  return bop3<kA & kB & kC>(g, mask0, mask1);
 }
 
 // Where a tile pass reads and writes cells.
@@ -176,10 +186,11 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
                                         uint32_t *lds, uint32_t *nseg_p) {
   uint32_t &nseg = *nseg_p;
   constexpr int kTbThreads = NT;
-  // Region columns [X0-16, X0+RHO+16): the tile plus one 16-cell chunk each
-  // side, in W words of 32 cells; word w starts at X0 - 16 + 32w, so its low
-  // and high halves each start on a multiple of 16.
-  constexpr int W = RHO / 32 + 1;     // region words per row
+  // Region columns [X0-32, X0+RHO+32): the tile plus one 32-cell word each
+  // side (a halo of up to 32 cells), word w starting at X0 - 32 + 32w, so
+  // every word starts on a multiple of 32 and holds the gasket pattern of
+  // its row whenever its first cell is on the gasket.
+  constexpr int W = RHO / 32 + 2;     // region words per row
   constexpr int PW = plane_pitch(W);  // plane pitch (at least one zero guard word each side)
   constexpr int CH = 2 * W;           // 16-byte chunks per region row
   constexpr int L = kSegRows;
@@ -190,6 +201,9 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   const int RP = NB * L;              // region rows rounded up to whole blocks
   const int PR = RP + 2;              // plane rows (zero guard row above, below)
   const int tid = threadIdx.x;
+  // chunks [jlo, jlo + CHL) of a region row lie within T cells of the tile
+  const int jlo = T > 16 ? 0 : 1;
+  const int CHL = CH - 2 * jlo;
 
   // n <= 2^20, so cell coordinates (halo included) fit in 32-bit ints
   const int n = 1 << r;
@@ -198,22 +212,21 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
 
   uint32_t *plane0 = lds;
   uint32_t *plane1 = lds + PR * PW;
-  uint32_t *rowpat = plane1 + PR * PW;  // RP: gasket pattern of each region row (both halves)
+  uint32_t *rowpat = plane1 + PR * PW;  // RP: gasket pattern of each region row
   uint32_t *segs = rowpat + RP;         // W * NB: listed segments
 
   mem.prepare(tid, bx, by, r - rho_log2_const(RHO));
   for (int i = tid; i < 2 * PR * PW; i += kTbThreads) lds[i] = 0u;
   for (int i = tid; i < RP; i += kTbThreads) {
     const int y = yr0 + i;
-    const uint32_t p16 = word_pattern((uint32_t)y & 15u) & 0xFFFFu;
-    rowpat[i] = (i < R && y >= 0 && y < n) ? (p16 | (p16 << 16)) : 0u;
+    rowpat[i] = (i < R && y >= 0 && y < n) ? word_pattern((uint32_t)y) : 0u;
   }
   if (tid == 0) nseg = 0u;
   __syncthreads();
 
   // 1. load and bit-pack the region, kLoadBatch loads in flight per thread
   uint16_t *p0h = reinterpret_cast<uint16_t *>(plane0);
-  for (int e0 = 0; e0 < R * CH; e0 += kTbThreads * kLoadBatch) {
+  for (int e0 = 0; e0 < R * CHL; e0 += kTbThreads * kLoadBatch) {
     uint4 v[kLoadBatch];
     int slot[kLoadBatch];
 #pragma unroll
@@ -221,9 +234,9 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
       const int e = e0 + q * kTbThreads + tid;
       slot[q] = -1;
       v[q] = make_uint4(0u, 0u, 0u, 0u);
-      if (e < R * CH) {
-        const int i = e / CH, j = e - (e / CH) * CH;
-        const int y = yr0 + i, x = X0 - 16 + 16 * j;
+      if (e < R * CHL) {
+        const int i = e / CHL, j = jlo + (e - (e / CHL) * CHL);
+        const int y = yr0 + i, x = X0 - 32 + 16 * j;
         if (y >= 0 && y < n && x >= 0 && x < n && (x & y) == 0) {
           v[q] = *reinterpret_cast<const uint4 *>(mem.src(y, x));
           slot[q] = ((i + 1) * PW + ((j >> 1) + 1)) * 2 + (j & 1);
@@ -236,23 +249,22 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   }
 
   // 2. compact list of the segments (word column w, rows [b*L, b*L+L)) that
-  //    hold a gasket cell, listed column by column; each entry keeps, per row
-  //    and per half word, whether that half's first cell is on the gasket
-  //    (then its cells are exactly those with (i & y) == 0)
+  //    hold a gasket cell, listed column by column; each entry keeps the rows
+  //    whose word starts on the gasket (then its cells are exactly those of
+  //    the row's pattern)
   const int lane = __lane_id();
   for (int base = 0; base < W * NB; base += kTbThreads) {
     const int e = base + tid;
     uint32_t rows = 0u, code = 0u;
     if (e < W * NB) {
       const int w = e / NB, b = e - (e / NB) * NB;
-      const int xlo = X0 - 16 + 32 * w, xhi = xlo + 16;
-      const bool lo_in = xlo >= 0 && xlo < n, hi_in = xhi < n;
+      const int xw = X0 - 32 + 32 * w;
+      if (xw >= 0 && xw < n) {
 #pragma unroll
-      for (int q = 0; q < L; ++q) {
-        const int i = b * L + q, y = yr0 + i;
-        if (rowpat[i] == 0u) continue;
-        if (lo_in && (xlo & y) == 0) rows |= 1u << q;
-        if (hi_in && (xhi & y) == 0) rows |= 1u << (q + 8);
+        for (int q = 0; q < L; ++q) {
+          const int i = b * L + q;
+          if (rowpat[i] != 0u && (xw & (yr0 + i)) == 0) rows |= 1u << q;
+        }
       }
       code = (uint32_t)w | ((uint32_t)b << 8) | (rows << 16);
     }
@@ -270,13 +282,14 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   for (int s = 0; s < T; ++s) {
     const uint32_t *src = (s & 1) ? plane1 : plane0;
     uint32_t *dst = (s & 1) ? plane0 : plane1;
-    // rows that can still reach the tile in the T-s-1 generations left:
-    // region rows [s+1, R-s-1); segments wholly outside are skipped
+    // cells that can still reach the tile in the T-s-1 generations left:
+    // region rows [s+1, R-s-1), and the halo words only while T-s-1 >= 1
     const int lo_row = s + 1, hi_row = R - s - 1;
+    const uint32_t w_lo = s + 1 < T ? 0u : 1u, w_span = W - 1 - 2 * w_lo;
     for (int k = tid; k < ns; k += kTbThreads) {
       const uint32_t code = segs[k];
       const int w = (int)(code & 0xffu), i0 = (int)((code >> 8) & 0xffu) * L;
-      if (i0 + L <= lo_row || i0 >= hi_row) continue;
+      if (i0 + L <= lo_row || i0 >= hi_row || (uint32_t)w - w_lo > w_span) continue;
       const uint32_t rows = code >> 16;
       const int idx0 = (i0 + 1) * PW + (w + 1);
       // all rows the segment reads, before any store (the planes may alias as
@@ -296,10 +309,8 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
 #pragma unroll
       for (int q = 0; q < L; ++q) {
         const RowSums dn = row_sums(row[q + 2][0], row[q + 2][1], row[q + 2][2]);
-        const uint32_t lo = (0u - ((rows >> q) & 1u)) & 0x0000FFFFu;
-        const uint32_t hi = (0u - ((rows >> (q + 8)) & 1u)) & 0xFFFF0000u;
-        const uint32_t m = pat[q] & (lo | hi);
-        dst[idx0 + q * PW] = life_rule(up, mid, dn) & m;
+        const uint32_t on = 0u - ((rows >> q) & 1u);
+        dst[idx0 + q * PW] = life_rule(up, mid, dn, pat[q], on);
         up = mid;
         mid = dn;
       }
@@ -316,7 +327,7 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
     // the embedding keeps granules without a gasket cell untouched; a compact
     // tile is rewritten whole
     if (!Mem::kCompact && ((x & ~63) & y) != 0) continue;
-    const int w = (j + 1) >> 1, half = (j + 1) & 1;  // region chunk j + 1
+    const int w = 1 + (j >> 1), half = j & 1;  // region chunk j + 2
     const uint32_t bits = fin[((T + ty + 1) * PW + (w + 1)) * 2 + half];
     *reinterpret_cast<uint4 *>(mem.dst(y, x)) = unpack16(bits);
   }

@@ -137,7 +137,7 @@ def test_ca_steps_validation(lib):
                ctypes.c_void_p(0x7100000000))
     r = 8  # n*n = 65536 bytes
     # steps_per_pass out of range, or > 1 where the tile side has no temporal blocking
-    assert lib.sg_ca_steps(0, r, 64, 10, 17, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 64, 10, 33, a, b, w, None) == sg.SG_EINVAL
     assert lib.sg_ca_steps(0, r, 64, 10, -1, a, b, w, None) == sg.SG_EINVAL
     assert lib.sg_ca_steps(0, r, 16, 10, 4, a, b, w, None) == sg.SG_EINVAL
     assert lib.sg_ca_steps(0, r, 32, 10, 2, a, b, w, None) == sg.SG_EINVAL
@@ -156,7 +156,7 @@ def test_batch_api_validation_on_the_host(lib):
     from paper_1706_04552_amd import sg
     t = sg.sg_tune()
     assert lib.sg_tune_default(ctypes.byref(t)) == sg.SG_OK
-    assert (t.rho, t.steps_per_pass, t.threads) == (64, 16, 256)
+    assert (t.rho, t.steps_per_pass, t.threads) == (64, 32, 256)
     assert lib.sg_tune_default(None) == sg.SG_EINVAL
     h = ctypes.c_void_p()
     a, b, w = 0x100000, 0x7000000000, 0x7100000000
@@ -169,7 +169,7 @@ def test_batch_api_validation_on_the_host(lib):
         return arr
 
     good = sg.sg_tune(64, 16, 0, 256)
-    for bad in [sg.sg_tune(32, 16, 0, 256), sg.sg_tune(64, 17, 0, 256), sg.sg_tune(64, 0, 0, 256),
+    for bad in [sg.sg_tune(32, 16, 0, 256), sg.sg_tune(64, 33, 0, 256), sg.sg_tune(64, 0, 0, 256),
                 sg.sg_tune(64, 16, -1, 256), sg.sg_tune(64, 16, 65, 256), sg.sg_tune(64, 16, 0, 128)]:
         assert lib.sg_batch_create(gaskets((8, 10, w)), 1, ctypes.byref(bad), ctypes.byref(h)) == sg.SG_EINVAL
     # gasket smaller than the tile, negative steps, missing work buffer, aliasing
@@ -265,7 +265,7 @@ def test_compact_storage_validation(lib):
                                  None) == sg.SG_EALIAS
     a, b, w = (ctypes.c_void_p(0x100000), ctypes.c_void_p(0x7000000000),
                ctypes.c_void_p(0x7100000000))
-    assert lib.sg_ca_steps_compact(r, rho, 10, 17, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps_compact(r, rho, 10, 33, a, b, w, None) == sg.SG_EINVAL
     assert lib.sg_ca_steps_compact(r, 32, 10, 4, a, b, w, None) == sg.SG_EINVAL
     assert lib.sg_ca_steps_compact(r, rho, -1, 4, a, b, w, None) == sg.SG_EINVAL
     assert lib.sg_ca_steps_compact(r, rho, 17, 16, a, b, None, None) == sg.SG_EINVAL

@@ -87,7 +87,8 @@ def test_batch_graph_replays_equal_eager_solo_and_oracle():
 
 @pytest.mark.parametrize("rho,spp,gpc,threads", [(64, 8, 0, 512), (128, 16, 4, 256),
                                                  (128, 5, 1, 512), (256, 16, 8, 256),
-                                                 (256, 16, 0, 512)])
+                                                 (256, 16, 0, 512), (256, 32, 2, 512),
+                                                 (64, 32, 0, 256)])
 def test_batch_launch_shapes_agree(rho, spp, gpc, threads):
     # levels 6..11: gaskets smaller than rho use tiles of their own side
     note(f"batch shapes rho={rho} per_pass={spp} groups_per_cu={gpc} threads={threads}")
@@ -106,7 +107,7 @@ def test_autotune_returns_a_valid_shape():
     hosts, gs = make_gaskets(16, 7, 10, 5, 30, 5)
     tune, ms = B.autotune(gs)
     assert ms > 0 and tune.rho in (64, 128, 256) and tune.threads in (256, 512)
-    assert 1 <= tune.steps_per_pass <= 16 and tune.groups_per_cu in (0, 2, 4, 8)
+    assert 1 <= tune.steps_per_pass <= 32 and tune.groups_per_cu in (0, 2, 4, 8)
     for g in gs:
         g.out.zero_()
         g.work.zero_()

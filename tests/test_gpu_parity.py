@@ -212,7 +212,9 @@ def gpu_ca_steps(map_kind, r, rho, a0, steps, spp):
 @pytest.mark.parametrize("r,rho,steps,spp", [
     (6, 64, 1, 16), (6, 64, 16, 16), (7, 64, 23, 8), (7, 128, 5, 5), (8, 256, 40, 16),
     (9, 64, 33, 16), (10, 128, 50, 16), (10, 256, 17, 16), (10, 64, 12, 1), (11, 128, 31, 7),
-    (8, 16, 9, 1), (9, 4, 3, 0), (10, 256, 0, 16), (12, 256, 100, 16), (12, 128, 100, 11)])
+    (8, 16, 9, 1), (9, 4, 3, 0), (10, 256, 0, 16), (12, 256, 100, 16), (12, 128, 100, 11),
+    (7, 64, 17, 17), (8, 64, 40, 32), (9, 128, 70, 24), (10, 256, 33, 32), (12, 256, 100, 32),
+    (11, 64, 64, 32)])
 def test_ca_steps_exact(map_kind, r, rho, steps, spp):
     note(f"ca_steps {map_kind} r={r} rho={rho} steps={steps} per_pass={spp}")
     a0 = inputs.bernoulli_state(r, 0.5, 1706 + 3 * r)
@@ -223,13 +225,13 @@ def test_ca_steps_exact(map_kind, r, rho, steps, spp):
 
 
 
-@pytest.mark.parametrize("r,rho", [(16, 256), (16, 128), (14, 64)])
-def test_ca_steps_full_size_sampled(r, rho):
+@pytest.mark.parametrize("r,rho,spp", [(16, 256, 16), (16, 256, 32), (16, 128, 16), (14, 64, 32)])
+def test_ca_steps_full_size_sampled(r, rho, spp):
     steps = 100
-    note(f"ca_steps full-size r={r} rho={rho} {steps} steps, 16 per pass")
+    note(f"ca_steps full-size r={r} rho={rho} {steps} steps, {spp} per pass")
     n = 1 << r
     a0 = inputs.bernoulli_state(r, 0.5, 1706)
-    tb = gpu_ca_steps("lambda", r, rho, a0, steps, 16)
+    tb = gpu_ca_steps("lambda", r, rho, a0, steps, spp)
     one = gpu_ca("lambda", r, rho, a0, steps)  # one launch per generation
     assert torch.equal(tb, one)
     del one
@@ -379,7 +381,8 @@ def gpu_ca_steps_compact(r, rho, a0, steps, spp):
 @pytest.mark.parametrize("r,rho,steps,spp", [
     (6, 64, 1, 16), (6, 64, 16, 16), (7, 64, 23, 8), (7, 128, 5, 5), (8, 256, 40, 16),
     (9, 64, 33, 16), (10, 128, 50, 16), (10, 256, 17, 16), (10, 64, 12, 1), (11, 128, 31, 7),
-    (10, 256, 0, 16), (12, 256, 100, 16), (12, 64, 100, 16)])
+    (10, 256, 0, 16), (12, 256, 100, 16), (12, 64, 100, 16), (10, 256, 64, 32),
+    (12, 128, 100, 32), (9, 64, 21, 21)])
 def test_ca_steps_compact_exact(r, rho, steps, spp):
     note(f"ca_steps_compact r={r} rho={rho} steps={steps} per_pass={spp}")
     a0 = inputs.bernoulli_state(r, 0.5, 1706 + 3 * r)
