@@ -41,6 +41,70 @@ __device__ __forceinline__ void lambda_decode(uint32_t w, int rb, uint32_t &bx,
   by = ly ^ ((1u << rb) - 1u);
 }
 
+// The pass kernels read the digits of their workgroup index in level order:
+// digit j is the region index beta at level mu = j + 1.  This is lambda
+// composed with a fixed relabelling of the W x H grid (the digit of level mu
+// belongs to omega_y for odd mu and to omega_x for even mu, Eq. 4, so the two
+// enumerate the same (omega_x, omega_y) pairs); it makes 3^m consecutive
+// workgroups one level-m sub-gasket of 2^m x 2^m blocks, so neighbouring
+// tiles run together.
+#ifndef SG_PASS_ORDER
+#define SG_PASS_ORDER 1
+#endif
+// Bits (x, y) of two consecutive levels for each base-9 digit d = d0 + 3 d1
+// (d0 the lower level): 2 bits per entry, entry d at bit 2d.
+constexpr uint32_t level_pair_table(bool x) {
+  uint32_t t = 0;
+  for (uint32_t d = 0; d < 9; ++d) {
+    const uint32_t d0 = d % 3, d1 = d / 3;
+    const uint32_t b = x ? ((d0 == 2) | ((d1 == 2) << 1)) : ((d0 != 0) | ((d1 != 0) << 1));
+    t |= b << (2 * d);
+  }
+  return t;
+}
+constexpr uint32_t kPairX = level_pair_table(true), kPairY = level_pair_table(false);
+
+__device__ __forceinline__ void lambda_decode_levels(uint32_t t, int rb, uint32_t &bx,
+                                                     uint32_t &by) {
+  // two levels per step: t mod 9 indexes the (x, y) bit pairs of levels
+  // 2i + 1 and 2i + 2; an odd rb ends with a digit d1 = 0
+  uint32_t lx = 0, ly = 0;
+  for (int j = 0; j < rb; j += 2) {
+    const uint32_t q = t / 9u;
+    const uint32_t d2 = (t - 9u * q) << 1;
+    t = q;
+    lx |= ((kPairX >> d2) & 3u) << j;
+    ly |= ((kPairY >> d2) & 3u) << j;
+  }
+  bx = lx;
+  by = ly ^ ((1u << rb) - 1u);
+}
+__device__ __forceinline__ void pass_decode(uint32_t t, int rb, uint32_t &bx, uint32_t &by) {
+#if SG_PASS_ORDER
+  lambda_decode_levels(t, rb, bx, by);
+#else
+  lambda_decode(t, rb, bx, by);
+#endif
+}
+
+// Logical index of this workgroup.  Workgroups are dispatched round robin
+// over the 8 XCDs (each with its own L2); renumbering them so that each XCD
+// runs one contiguous range of the logical order keeps neighbouring tiles,
+// which share halo rows, in one L2.
+#ifndef SG_XCD_REMAP
+#define SG_XCD_REMAP 1
+#endif
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t logical_group() {
+#if SG_XCD_REMAP
+  const uint32_t G = gridDim.x, g = blockIdx.x;
+  const uint32_t q = G / kXcds, rm = G % kXcds, x = g % kXcds;
+  return x * q + (x < rm ? x : rm) + g / kXcds;
+#else
+  return blockIdx.x;
+#endif
+}
+
 // Inverse of lambda_decode: the linear omega of the fractal block (bx, by)
 // (build frame, bx & by == 0).  In the paper frame, bit mu-1 of
 // (lambda_x, lambda_y) is (Delta^x_mu, Delta^y_mu), so the region index at

@@ -47,11 +47,11 @@ __global__ __launch_bounds__(kDtThreads) void k_diffuse_tb(const float *__restri
   using G = DtGeom<RHO>;
   extern __shared__ float flds[];
   __shared__ uint32_t nchunk;
-  const uint64_t t = tile_base + blockIdx.x;
+  const uint64_t t = tile_base + logical_group();
   if (t >= ntiles) return;
   uint32_t bx, by;
   if constexpr (LAMBDA) {
-    lambda_decode((uint32_t)t, rb, bx, by);
+    pass_decode((uint32_t)t, rb, bx, by);
   } else {
     by = (uint32_t)(t >> rb);
     bx = (uint32_t)(t & ((1ull << rb) - 1ull));

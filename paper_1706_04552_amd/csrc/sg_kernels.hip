@@ -32,10 +32,10 @@ template <bool LAMBDA>
 __device__ __forceinline__ bool tile_of(uint64_t tile_base, uint64_t ntiles,
                                         int tpg, int slot, int rb, uint32_t &bx,
                                         uint32_t &by) {
-  const uint64_t t = tile_base + (uint64_t)blockIdx.x * (uint64_t)tpg + (uint64_t)slot;
+  const uint64_t t = tile_base + (uint64_t)logical_group() * (uint64_t)tpg + (uint64_t)slot;
   if (t >= ntiles) return false;
   if constexpr (LAMBDA) {
-    lambda_decode((uint32_t)t, rb, bx, by);
+    pass_decode((uint32_t)t, rb, bx, by);
     return true;
   } else {
     by = (uint32_t)(t >> rb);
@@ -67,11 +67,11 @@ __global__ __launch_bounds__(kWG) void k_map_bbox(uint8_t *__restrict__ mask,
 
 // ------------------------------------------------------------------ write pass
 
-template <int RHO, bool LAMBDA>
-__global__ __launch_bounds__(kWG) void k_write(uint8_t *__restrict__ a, int r,
+template <int RHO, bool LAMBDA, int NT>
+__global__ __launch_bounds__(NT) void k_write(uint8_t *__restrict__ a, int r,
                                                int rb, uint64_t tile_base,
                                                uint64_t ntiles, uint32_t value) {
-  constexpr int TPG = kWG / RHO;
+  constexpr int TPG = NT / RHO;
   const int slot = threadIdx.x / RHO;
   const uint32_t ty = threadIdx.x % RHO;
   uint32_t bx, by;
@@ -117,12 +117,12 @@ __device__ __forceinline__ void shift_in_right(U8Row<RHO> &o, const U8Row<RHO> &
 
 __device__ __forceinline__ bool on_gasket(size_t x, size_t y) { return (x & y) == 0; }
 
-template <int RHO, bool LAMBDA>
-__global__ __launch_bounds__(kWG) void k_life(const uint8_t *__restrict__ in,
+template <int RHO, bool LAMBDA, int NT>
+__global__ __launch_bounds__(NT) void k_life(const uint8_t *__restrict__ in,
                                               uint8_t *__restrict__ out, int r,
                                               int rb, uint64_t tile_base,
                                               uint64_t ntiles) {
-  constexpr int TPG = kWG / RHO;
+  constexpr int TPG = NT / RHO;
   constexpr int NW = U8Row<RHO>::NW;
   const int slot = threadIdx.x / RHO;
   const uint32_t ty = threadIdx.x % RHO;
@@ -135,13 +135,30 @@ __global__ __launch_bounds__(kWG) void k_life(const uint8_t *__restrict__ in,
   const bool has_l = X0 > 0, has_r = X0 + RHO < n;
   const size_t xl = X0 - 1, xr = X0 + RHO;
 
-  // own row and its left/right neighbour cells (neighbouring tiles)
-  U8Row<RHO> C;
+  // every load of the lane is issued before the first wait: its own row and
+  // left/right neighbour cells, and, on the tile's first / last row, the halo
+  // row above / below with its corner cells
+  U8Row<RHO> C, HU, HD;
+  zero_row<RHO>(HU);
+  zero_row<RHO>(HD);
   load_row<RHO>(C, in + y * n + X0);
   uint32_t cl = (has_l && on_gasket(xl, y)) ? in[y * n + xl] : 0u;
   uint32_t cr = (has_r && on_gasket(xr, y)) ? in[y * n + xr] : 0u;
+  uint32_t hul = 0u, hur = 0u, hdl = 0u, hdr = 0u;
+  if (ty == 0 && Y0 > 0) {
+    const size_t yu = Y0 - 1;
+    if (on_gasket(X0, yu)) load_row<RHO>(HU, in + yu * n + X0);
+    if (has_l && on_gasket(xl, yu)) hul = in[yu * n + xl];
+    if (has_r && on_gasket(xr, yu)) hur = in[yu * n + xr];
+  }
+  if (ty == RHO - 1 && Y0 + RHO < n) {
+    const size_t yd = Y0 + RHO;
+    if (on_gasket(X0, yd)) load_row<RHO>(HD, in + yd * n + X0);
+    if (has_l && on_gasket(xl, yd)) hdl = in[yd * n + xl];
+    if (has_r && on_gasket(xr, yd)) hdr = in[yd * n + xr];
+  }
 
-  // rows above / below: neighbouring lanes, or a halo row for the tile edges
+  // rows above / below: neighbouring lanes, or the halo row at the tile edges
   U8Row<RHO> U, D;
   uint32_t ul = from_prev_lane(cl), ur = from_prev_lane(cr);
   uint32_t dl = from_next_lane(cl), dr = from_next_lane(cr);
@@ -151,24 +168,14 @@ __global__ __launch_bounds__(kWG) void k_life(const uint8_t *__restrict__ in,
     D.w[k] = from_next_lane(C.w[k]);
   }
   if (ty == 0) {
-    zero_row<RHO>(U);
-    ul = ur = 0u;
-    if (Y0 > 0) {
-      const size_t yu = Y0 - 1;
-      if (on_gasket(X0, yu)) load_row<RHO>(U, in + yu * n + X0);
-      if (has_l && on_gasket(xl, yu)) ul = in[yu * n + xl];
-      if (has_r && on_gasket(xr, yu)) ur = in[yu * n + xr];
-    }
+    U = HU;
+    ul = hul;
+    ur = hur;
   }
   if (ty == RHO - 1) {
-    zero_row<RHO>(D);
-    dl = dr = 0u;
-    if (Y0 + RHO < n) {
-      const size_t yd = Y0 + RHO;
-      if (on_gasket(X0, yd)) load_row<RHO>(D, in + yd * n + X0);
-      if (has_l && on_gasket(xl, yd)) dl = in[yd * n + xl];
-      if (has_r && on_gasket(xr, yd)) dr = in[yd * n + xr];
-    }
+    D = HD;
+    dl = hdl;
+    dr = hdr;
   }
 
   // column sums of the 3 rows, then the 3-wide horizontal sum (bytes <= 9)
@@ -230,12 +237,12 @@ __device__ __forceinline__ void store_frow(float *p, const F32Row<RHO> &row) {
   }
 }
 
-template <int RHO, bool LAMBDA>
-__global__ __launch_bounds__(kWG) void k_diffuse(const float *__restrict__ in,
+template <int RHO, bool LAMBDA, int NT>
+__global__ __launch_bounds__(NT) void k_diffuse(const float *__restrict__ in,
                                                  float *__restrict__ out, int r,
                                                  int rb, uint64_t tile_base,
                                                  uint64_t ntiles, float alpha) {
-  constexpr int TPG = kWG / RHO;
+  constexpr int TPG = NT / RHO;
   const int slot = threadIdx.x / RHO;
   const uint32_t ty = threadIdx.x % RHO;
   uint32_t bx, by;
@@ -248,26 +255,24 @@ __global__ __launch_bounds__(kWG) void k_diffuse(const float *__restrict__ in,
   const bool has_u = y > 0, has_d = y + 1 < n;
   const size_t xl = X0 - 1, xr = X0 + RHO;
 
-  F32Row<RHO> C, U, D, O;
+  // all loads first (own row, left/right cells, halo rows at the tile edges)
+  F32Row<RHO> C, U, D, O, HU, HD;
+#pragma unroll
+  for (int i = 0; i < RHO; ++i) HU.v[i] = HD.v[i] = 0.0f;
   load_frow<RHO>(C, in + y * n + X0);
   const bool ml = has_l && on_gasket(xl, y), mr = has_r && on_gasket(xr, y);
   const float cl = ml ? in[y * n + xl] : 0.0f;
   const float cr = mr ? in[y * n + xr] : 0.0f;
+  if (ty == 0 && Y0 > 0 && on_gasket(X0, Y0 - 1)) load_frow<RHO>(HU, in + (Y0 - 1) * n + X0);
+  if (ty == RHO - 1 && Y0 + RHO < n && on_gasket(X0, Y0 + RHO))
+    load_frow<RHO>(HD, in + (Y0 + RHO) * n + X0);
 #pragma unroll
   for (int i = 0; i < RHO; ++i) {
     U.v[i] = from_prev_lane(C.v[i]);
     D.v[i] = from_next_lane(C.v[i]);
   }
-  if (ty == 0) {
-#pragma unroll
-    for (int i = 0; i < RHO; ++i) U.v[i] = 0.0f;
-    if (Y0 > 0 && on_gasket(X0, Y0 - 1)) load_frow<RHO>(U, in + (Y0 - 1) * n + X0);
-  }
-  if (ty == RHO - 1) {
-#pragma unroll
-    for (int i = 0; i < RHO; ++i) D.v[i] = 0.0f;
-    if (Y0 + RHO < n && on_gasket(X0, Y0 + RHO)) load_frow<RHO>(D, in + (Y0 + RHO) * n + X0);
-  }
+  if (ty == 0) U = HU;
+  if (ty == RHO - 1) D = HD;
 
 #pragma unroll
   for (int i = 0; i < RHO; ++i) {
@@ -302,19 +307,19 @@ struct Granules {
   static constexpr int LOAD = ROW_BYTES >= 128 ? 128 : (ROW_BYTES >= 64 ? 64 : 16);
 };
 
-template <int RHO, int CHUNK>
+template <int RHO, int CHUNK, int NT>
 struct Strip {
   static constexpr int CPR = RHO / CHUNK;         // chunks per tile row
   static constexpr int LPT = CPR * (RHO / kBand); // lanes per tile
-  static constexpr int WGS = LPT > kWG ? LPT : kWG;
+  static constexpr int WGS = LPT > NT ? LPT : NT;
   static constexpr int TPG = WGS / LPT;           // tiles per workgroup
 };
 
-template <int RHO, bool LAMBDA>
-__global__ __launch_bounds__((Strip<RHO, 16>::WGS)) void k_write_strip(
+template <int RHO, bool LAMBDA, int NT>
+__global__ __launch_bounds__((Strip<RHO, 16, NT>::WGS)) void k_write_strip(
     uint8_t *__restrict__ a, int r, int rb, uint64_t tile_base, uint64_t ntiles,
     uint32_t value) {
-  using G = Strip<RHO, 16>;
+  using G = Strip<RHO, 16, NT>;
   const int slot = threadIdx.x / G::LPT, lt = threadIdx.x % G::LPT;
   const int band = lt / G::CPR, c = lt % G::CPR;
   uint32_t bx, by;
@@ -336,11 +341,11 @@ __global__ __launch_bounds__((Strip<RHO, 16>::WGS)) void k_write_strip(
   }
 }
 
-template <int RHO, bool LAMBDA>
-__global__ __launch_bounds__((Strip<RHO, 16>::WGS)) void k_life_strip(
+template <int RHO, bool LAMBDA, int NT>
+__global__ __launch_bounds__((Strip<RHO, 16, NT>::WGS)) void k_life_strip(
     const uint8_t *__restrict__ in, uint8_t *__restrict__ out, int r, int rb,
     uint64_t tile_base, uint64_t ntiles) {
-  using G = Strip<RHO, 16>;
+  using G = Strip<RHO, 16, NT>;
   const int slot = threadIdx.x / G::LPT, lt = threadIdx.x % G::LPT;
   const int band = lt / G::CPR, c = lt % G::CPR;
   uint32_t bx, by;
@@ -394,11 +399,11 @@ __global__ __launch_bounds__((Strip<RHO, 16>::WGS)) void k_life_strip(
   }
 }
 
-template <int RHO, bool LAMBDA>
-__global__ __launch_bounds__((Strip<RHO, 4>::WGS)) void k_diffuse_strip(
+template <int RHO, bool LAMBDA, int NT>
+__global__ __launch_bounds__((Strip<RHO, 4, NT>::WGS)) void k_diffuse_strip(
     const float *__restrict__ in, float *__restrict__ out, int r, int rb,
     uint64_t tile_base, uint64_t ntiles, float alpha) {
-  using G = Strip<RHO, 4>;
+  using G = Strip<RHO, 4, NT>;
   const int slot = threadIdx.x / G::LPT, lt = threadIdx.x % G::LPT;
   const int band = lt / G::CPR, c = lt % G::CPR;
   uint32_t bx, by;
@@ -470,69 +475,72 @@ hipError_t launch_tiles(uint64_t ntiles, int tpg, hipStream_t s, F &&launch_one)
   return hipSuccess;
 }
 
+// Workgroup size of a one-step pass: launches of fewer than kSmallLaunchWaves
+// waves (small gaskets, where a pass is one latency chain) run one wave per
+// workgroup, so they spread over more CUs; larger launches run four.
+constexpr uint64_t kSmallLaunchWaves = 2048;
+inline bool small_launch(uint64_t ntiles, int lanes_per_tile) {
+  return ntiles * (uint64_t)lanes_per_tile < kSmallLaunchWaves * 64;
+}
+
+// Launches kernel K<NT> over all tiles with NT = 64 or 256 threads per group.
+#define SG_LAUNCH_PASS(KERNEL, TPG_OF, WGS_OF, LANES, ...)                                 \
+  do {                                                                                     \
+    if (small_launch(a.ntiles, LANES))                                                     \
+      return launch_tiles(a.ntiles, TPG_OF(64), a.stream, [&](dim3 g, uint64_t base, hipStream_t s) { \
+        if (a.lambda)                                                                      \
+          hipLaunchKernelGGL((KERNEL<RHO, true, 64>), g, dim3(WGS_OF(64)), 0, s, __VA_ARGS__); \
+        else                                                                               \
+          hipLaunchKernelGGL((KERNEL<RHO, false, 64>), g, dim3(WGS_OF(64)), 0, s, __VA_ARGS__); \
+      });                                                                                  \
+    return launch_tiles(a.ntiles, TPG_OF(256), a.stream, [&](dim3 g, uint64_t base, hipStream_t s) { \
+      if (a.lambda)                                                                        \
+        hipLaunchKernelGGL((KERNEL<RHO, true, 256>), g, dim3(WGS_OF(256)), 0, s, __VA_ARGS__); \
+      else                                                                                 \
+        hipLaunchKernelGGL((KERNEL<RHO, false, 256>), g, dim3(WGS_OF(256)), 0, s, __VA_ARGS__); \
+    });                                                                                    \
+  } while (0)
+
+#define SG_ROWS_TPG(NT) ((NT) / RHO)
+#define SG_ROWS_WGS(NT) (NT)
+#define SG_STRIP16_TPG(NT) (Strip<RHO, 16, NT>::TPG)
+#define SG_STRIP16_WGS(NT) (Strip<RHO, 16, NT>::WGS)
+#define SG_STRIP4_TPG(NT) (Strip<RHO, 4, NT>::TPG)
+#define SG_STRIP4_WGS(NT) (Strip<RHO, 4, NT>::WGS)
+
 template <int RHO>
 hipError_t write_strip(const PassArgs &a, uint8_t *d, uint32_t value) {
-  using G = Strip<RHO, 16>;
-  return launch_tiles(a.ntiles, G::TPG, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
-    if (a.lambda)
-      hipLaunchKernelGGL((k_write_strip<RHO, true>), grid, dim3(G::WGS), 0, s, d, a.r, a.rb, base, a.ntiles, value);
-    else
-      hipLaunchKernelGGL((k_write_strip<RHO, false>), grid, dim3(G::WGS), 0, s, d, a.r, a.rb, base, a.ntiles, value);
-  });
+  SG_LAUNCH_PASS(k_write_strip, SG_STRIP16_TPG, SG_STRIP16_WGS, (Strip<RHO, 16, 64>::LPT),
+                 d, a.r, a.rb, base, a.ntiles, value);
 }
 
 template <int RHO>
 hipError_t life_strip(const PassArgs &a, const uint8_t *in, uint8_t *out) {
-  using G = Strip<RHO, 16>;
-  return launch_tiles(a.ntiles, G::TPG, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
-    if (a.lambda)
-      hipLaunchKernelGGL((k_life_strip<RHO, true>), grid, dim3(G::WGS), 0, s, in, out, a.r, a.rb, base, a.ntiles);
-    else
-      hipLaunchKernelGGL((k_life_strip<RHO, false>), grid, dim3(G::WGS), 0, s, in, out, a.r, a.rb, base, a.ntiles);
-  });
+  SG_LAUNCH_PASS(k_life_strip, SG_STRIP16_TPG, SG_STRIP16_WGS, (Strip<RHO, 16, 64>::LPT),
+                 in, out, a.r, a.rb, base, a.ntiles);
 }
 
 template <int RHO>
 hipError_t diffuse_strip(const PassArgs &a, const float *in, float *out, float alpha) {
-  using G = Strip<RHO, 4>;
-  return launch_tiles(a.ntiles, G::TPG, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
-    if (a.lambda)
-      hipLaunchKernelGGL((k_diffuse_strip<RHO, true>), grid, dim3(G::WGS), 0, s, in, out, a.r, a.rb, base, a.ntiles, alpha);
-    else
-      hipLaunchKernelGGL((k_diffuse_strip<RHO, false>), grid, dim3(G::WGS), 0, s, in, out, a.r, a.rb, base, a.ntiles, alpha);
-  });
+  SG_LAUNCH_PASS(k_diffuse_strip, SG_STRIP4_TPG, SG_STRIP4_WGS, (Strip<RHO, 4, 64>::LPT),
+                 in, out, a.r, a.rb, base, a.ntiles, alpha);
 }
 
 template <int RHO>
 hipError_t write_rho(const PassArgs &a, uint8_t *d, uint32_t value) {
-  return launch_tiles(a.ntiles, kWG / RHO, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
-    if (a.lambda)
-      hipLaunchKernelGGL((k_write<RHO, true>), grid, dim3(kWG), 0, s, d, a.r, a.rb, base, a.ntiles, value);
-    else
-      hipLaunchKernelGGL((k_write<RHO, false>), grid, dim3(kWG), 0, s, d, a.r, a.rb, base, a.ntiles, value);
-  });
+  SG_LAUNCH_PASS(k_write, SG_ROWS_TPG, SG_ROWS_WGS, RHO, d, a.r, a.rb, base, a.ntiles, value);
 }
 
 template <int RHO>
 hipError_t life_rho(const PassArgs &a, const uint8_t *in, uint8_t *out) {
-  return launch_tiles(a.ntiles, kWG / RHO, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
-    if (a.lambda)
-      hipLaunchKernelGGL((k_life<RHO, true>), grid, dim3(kWG), 0, s, in, out, a.r, a.rb, base, a.ntiles);
-    else
-      hipLaunchKernelGGL((k_life<RHO, false>), grid, dim3(kWG), 0, s, in, out, a.r, a.rb, base, a.ntiles);
-  });
+  SG_LAUNCH_PASS(k_life, SG_ROWS_TPG, SG_ROWS_WGS, RHO, in, out, a.r, a.rb, base, a.ntiles);
 }
 
 template <int RHO>
 hipError_t diffuse_rho(const PassArgs &a, const float *in, float *out, float alpha) {
-  return launch_tiles(a.ntiles, kWG / RHO, a.stream, [&](dim3 grid, uint64_t base, hipStream_t s) {
-    if (a.lambda)
-      hipLaunchKernelGGL((k_diffuse<RHO, true>), grid, dim3(kWG), 0, s, in, out, a.r, a.rb, base, a.ntiles, alpha);
-    else
-      hipLaunchKernelGGL((k_diffuse<RHO, false>), grid, dim3(kWG), 0, s, in, out, a.r, a.rb, base, a.ntiles, alpha);
-  });
+  SG_LAUNCH_PASS(k_diffuse, SG_ROWS_TPG, SG_ROWS_WGS, RHO, in, out, a.r, a.rb, base, a.ntiles,
+                 alpha);
 }
-
 
 // ------------------------------------------------------------------ intra-block variants
 //

@@ -341,11 +341,11 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__
                                                                uint64_t ntiles, int T) {
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t nseg;
-  const uint64_t t = tile_base + blockIdx.x;
+  const uint64_t t = tile_base + logical_group();
   if (t >= ntiles) return;
   uint32_t bx, by;
   if constexpr (LAMBDA) {
-    lambda_decode((uint32_t)t, rb, bx, by);
+    pass_decode((uint32_t)t, rb, bx, by);
   } else {
     by = (uint32_t)(t >> rb);
     bx = (uint32_t)(t & ((1ull << rb) - 1ull));
@@ -363,10 +363,10 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb_compact(
   extern __shared__ uint32_t lds[];
   __shared__ uint32_t nseg;
   __shared__ int32_t nbr[9];
-  const uint64_t t = tile_base + blockIdx.x;
+  const uint64_t t = tile_base + logical_group();
   if (t >= ntiles) return;
   uint32_t bx, by;
-  lambda_decode((uint32_t)t, rb, bx, by);
+  lambda_decode((uint32_t)t, rb, bx, by);  // storage order
   const CompactMem<RHO> mem{in, out, nbr, (int)bx, (int)by};
   tb_tile<RHO, tb_threads<RHO>()>(mem, r, bx, by, T, lds, &nseg);
 }
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restric
     }
     const BatchItem it = items[lo];
     uint32_t bx, by;
-    lambda_decode((uint32_t)(g - it.tile_begin), it.r - it.k, bx, by);
+    pass_decode((uint32_t)(g - it.tile_begin), it.r - it.k, bx, by);
     if (it.k == 6) {
       tb_tile<64, NT>(DenseMem{it.src, it.dst, 1 << it.r}, it.r, bx, by, it.steps, lds, &nseg);
     } else if (MAXRHO >= 128 && it.k == 7) {
