@@ -223,7 +223,8 @@ def bench_batched(torch, sg, inputs, count, steps, runs):
     return out
 
 
-def bench_serving(torch, sg, inputs, qps_list, count, cap_gb):
+def bench_serving(torch, sg, inputs, qps_list, count, cap_gb, horizon_cells=None,
+                  budget_cells=None):
     """Poisson arrivals of life solves (r ~ U{8..15}, steps ~ U{10..200}) served
     by continuous batching under an HBM footprint cap, against one request at
     a time on the same arrivals (FIFO, each request's measured service time
@@ -245,9 +246,12 @@ def bench_serving(torch, sg, inputs, qps_list, count, cap_gb):
         reqs = inputs.poisson_requests(qps, count)
         rq = [serving.Request(q.rid, q.arrival, q.r, q.steps, template=q.r) for q in reqs]
         ex = serving.GpuExecutor(tune, capacity=count, templates=templates)
+        ex.reserve([q.r for q in rq], int(cap_gb * 1e9))  # the server's memory pool
         server = serving.ContinuousBatcher(ex, cap_bytes=int(cap_gb * 1e9),
-                                           steps_per_pass=tune.steps_per_pass)
-        server.serve(rq[:16])  # warm-up (fills the buffer pool a little)
+                                           steps_per_pass=tune.steps_per_pass,
+                                           horizon_cells=horizon_cells,
+                                           max_cells_per_pass=budget_cells)
+        server.serve(rq[:16])  # warm-up (first-call costs)
         stats = server.serve(rq)
         summ = stats.summary()
         # one request at a time: each request alone (state copy + its steps)
@@ -280,7 +284,8 @@ def bench_serving(torch, sg, inputs, qps_list, count, cap_gb):
         results.append(summ)
         del ex
         torch.cuda.empty_cache()
-    return {"tune": tune.as_dict(), "requests": count, "by_qps": results}
+    return {"tune": tune.as_dict(), "requests": count, "horizon_cells": horizon_cells,
+            "budget_cells": budget_cells, "by_qps": results}
 
 
 def main():
@@ -299,6 +304,10 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-qps", type=float, nargs="*", default=[1000.0, 4000.0, 16000.0])
     ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-horizon", type=float, default=4e9,
+                    help="cell updates queued per scheduling round (0: one pass per round)")
+    ap.add_argument("--serve-budget", type=float, default=2e9,
+                    help="cell updates per batched pass, oldest requests first (0: no budget)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -431,7 +440,9 @@ def main():
         extras["diffusion"] = bench_diffusion(torch, sg, inputs, (16, 64, 128, 256), args.steps, args.warmup)
         extras["batched"] = bench_batched(torch, sg, inputs, args.batch_count, 50, 5)
         torch.cuda.empty_cache()
-        extras["serving"] = bench_serving(torch, sg, inputs, args.serve_qps, args.serve_requests, 200.0)
+        extras["serving"] = bench_serving(torch, sg, inputs, args.serve_qps, args.serve_requests, 200.0,
+                                          int(args.serve_horizon) or None,
+                                          int(args.serve_budget) or None)
         torch.cuda.empty_cache()
 
     cpu = None

@@ -288,14 +288,17 @@ SG_API void sg_batch_destroy(sg_batch *batch);
 SG_API int sg_batch_autotune(const sg_gasket *gaskets, int count, sg_tune *best,
                              float *best_ms, void *stream);
 
-/* Device item table for up to `capacity` gaskets per pass (continuous
- * batching: the set of gaskets changes from pass to pass).  Allocates device
- * and pinned host memory.  Errors: SG_EINVAL, SG_ENOMEM, SG_EHIP. */
+/* Device item tables for up to `capacity` gaskets per pass (continuous
+ * batching: the set of gaskets changes from pass to pass), in a ring of 8
+ * upload slots so that up to 8 passes can be queued ahead of the GPU.
+ * Allocates device and pinned host memory.  Errors: SG_EINVAL, SG_ENOMEM,
+ * SG_EHIP. */
 SG_API int sg_pass_ctx_create(int capacity, sg_pass_ctx **out);
 
 /* One batched pass over `count` items (host array, validated, then uploaded
- * asynchronously on `stream`).  Successive calls on one context must use
- * the same stream.  Errors: SG_EINVAL (count > capacity, steps outside
+ * asynchronously on `stream`; returns once the items are staged, blocking
+ * only until the upload of the pass queued 8 calls earlier has run).  Successive
+ * calls on one context must use the same stream.  Errors: SG_EINVAL (count > capacity, steps outside
  * 0..steps_per_pass, r < 6 or r > SG_MAX_R), SG_EALIAS, SG_EHIP. */
 SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
                        const sg_tune *tune, void *stream);

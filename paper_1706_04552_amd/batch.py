@@ -5,6 +5,7 @@ import ctypes
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import sg
@@ -25,6 +26,11 @@ def _ptr(t: Optional[torch.Tensor], r: int, name: str):
     if t is None:
         return None
     return sg._dev(t, torch.uint8, (1 << r) * (1 << r), name)
+
+
+def checked_ptr(t: torch.Tensor, r: int, name: str) -> int:
+    """Device address of an n x n uint8 CUDA tensor (checked), for PASS_ITEM arrays."""
+    return _ptr(t, r, name).value
 
 
 def _gasket_array(gaskets: Sequence[Gasket]):
@@ -98,6 +104,12 @@ class Batch:
         self.close()
 
 
+# numpy layout of sg_pass_item
+PASS_ITEM = np.dtype([("src", np.uint64), ("dst", np.uint64), ("r", np.int32),
+                      ("steps", np.int32)])
+assert PASS_ITEM.itemsize == ctypes.sizeof(sg.sg_pass_item)
+
+
 class PassContext:
     """Device item table for repeated batched passes over a changing set of
     gaskets (continuous batching)."""
@@ -107,6 +119,15 @@ class PassContext:
         sg._check(sg.load().sg_pass_ctx_create(capacity, ctypes.byref(h)), "sg_pass_ctx_create")
         self._h = h
         self.capacity = capacity
+
+    def run_array(self, items: np.ndarray, tune, stream=None):
+        """items: a C-contiguous PASS_ITEM array of raw device pointers (taken
+        from checked tensors by the caller), r and steps."""
+        if items.dtype != PASS_ITEM or not items.flags.c_contiguous:
+            raise TypeError("items must be a C-contiguous PASS_ITEM array")
+        ptr = items.ctypes.data_as(ctypes.POINTER(sg.sg_pass_item))
+        sg._check(sg.load().sg_pass_run(self._h, ptr, len(items), ctypes.byref(tune),
+                                        sg._stream(stream)), "sg_pass_run")
 
     def run(self, items: List[tuple], tune, stream=None):
         """items: (src, dst, r, steps) with src/dst uint8 device tensors."""

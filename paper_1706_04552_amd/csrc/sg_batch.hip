@@ -191,12 +191,18 @@ struct sg_batch {
   hipGraphExec_t exec = nullptr;
 };
 
+// A ring of upload slots, each with its own pinned staging area, device
+// table and event, so the host can queue up to kPassRing passes ahead of the
+// GPU: pass i uses slot i mod kPassRing and waits only for the upload that
+// used the slot kPassRing passes earlier.
+constexpr int kPassRing = 8;
 struct sg_pass_ctx {
   int capacity = 0;
-  sg::BatchItem *d_items = nullptr;
-  sg::BatchItem *h_stage = nullptr;  // pinned staging for the asynchronous upload
-  hipEvent_t staged = nullptr;       // the last upload has read h_stage
-  bool pending = false;
+  int next = 0;                                  // slot of the next pass
+  sg::BatchItem *d_items = nullptr;              // kPassRing tables of `capacity` items
+  sg::BatchItem *h_stage = nullptr;              // pinned staging, same shape
+  hipEvent_t staged[kPassRing] = {};             // slot's last upload has read its staging
+  bool pending[kPassRing] = {};
 };
 
 extern "C" {
@@ -330,12 +336,13 @@ SG_API int sg_pass_ctx_create(int capacity, sg_pass_ctx **out) {
   *out = nullptr;
   sg_pass_ctx *c = new sg_pass_ctx();
   c->capacity = capacity;
-  const size_t bytes = (size_t)capacity * sizeof(sg::BatchItem);
+  const size_t bytes = (size_t)kPassRing * (size_t)capacity * sizeof(sg::BatchItem);
   int st = SG_OK;
   if (hipMalloc((void **)&c->d_items, bytes) != hipSuccess) st = SG_ENOMEM;
   if (st == SG_OK && hipHostMalloc((void **)&c->h_stage, bytes, hipHostMallocDefault) != hipSuccess)
     st = SG_ENOMEM;
-  if (st == SG_OK) st = hip_err(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming));
+  for (int k = 0; k < kPassRing && st == SG_OK; ++k)
+    st = hip_err(hipEventCreateWithFlags(&c->staged[k], hipEventDisableTiming));
   if (st != SG_OK) {
     sg_pass_ctx_destroy(c);
     return st;
@@ -365,7 +372,10 @@ SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
   if (live == 0) return SG_OK;
   if (sg::inject_hip_error()) return SG_EHIP;
   hipStream_t s = (hipStream_t)stream;
-  if (ctx->pending && hipEventSynchronize(ctx->staged) != hipSuccess) return SG_EHIP;
+  const int slot = ctx->next;
+  if (ctx->pending[slot] && hipEventSynchronize(ctx->staged[slot]) != hipSuccess) return SG_EHIP;
+  sg::BatchItem *h_stage = ctx->h_stage + (size_t)slot * ctx->capacity;
+  sg::BatchItem *d_items = ctx->d_items + (size_t)slot * ctx->capacity;
   uint64_t tiles = 0;
   int m = 0;
   for (int i = 0; i < count; ++i) {
@@ -379,22 +389,25 @@ SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
     b.k = (int16_t)item_k(it.r, kmax);
     b.tile_begin = tiles;
     tiles += pow3(it.r - b.k);
-    ctx->h_stage[m++] = b;
+    h_stage[m++] = b;
   }
-  st = hip_err(hipMemcpyAsync(ctx->d_items, ctx->h_stage, (size_t)m * sizeof(sg::BatchItem),
+  st = hip_err(hipMemcpyAsync(d_items, h_stage, (size_t)m * sizeof(sg::BatchItem),
                               hipMemcpyHostToDevice, s));
   if (st != SG_OK) return st;
-  st = hip_err(hipEventRecord(ctx->staged, s));
+  st = hip_err(hipEventRecord(ctx->staged[slot], s));
   if (st != SG_OK) return st;
-  ctx->pending = true;
-  return hip_err(sg::launch_life_tb_batch(tune->rho, tune->threads, ctx->d_items, m, tiles,
+  ctx->pending[slot] = true;
+  ctx->next = (slot + 1) % kPassRing;
+  return hip_err(sg::launch_life_tb_batch(tune->rho, tune->threads, d_items, m, tiles,
                                           max_steps, groups_for(*tune, tiles), s));
 }
 
 SG_API void sg_pass_ctx_destroy(sg_pass_ctx *ctx) {
   if (!ctx) return;
-  if (ctx->pending && ctx->staged) (void)hipEventSynchronize(ctx->staged);
-  if (ctx->staged) (void)hipEventDestroy(ctx->staged);
+  for (int k = 0; k < kPassRing; ++k) {
+    if (ctx->pending[k] && ctx->staged[k]) (void)hipEventSynchronize(ctx->staged[k]);
+    if (ctx->staged[k]) (void)hipEventDestroy(ctx->staged[k]);
+  }
   if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
   if (ctx->d_items) (void)hipFree(ctx->d_items);
   delete ctx;

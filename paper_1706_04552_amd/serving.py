@@ -64,7 +64,8 @@ class _Slot:
 class ServeStats:
     results: List[Result] = field(default_factory=list)
     makespan: float = 0.0
-    iterations: int = 0
+    iterations: int = 0      # scheduling rounds (one device wait each)
+    passes: int = 0          # batched passes
     max_resident_bytes: int = 0
     max_active: int = 0
 
@@ -77,7 +78,8 @@ class ServeStats:
                 "p99_ms": float(np.percentile(lat, 99) * 1e3),
                 "mean_ms": float(lat.mean() * 1e3),
                 "makespan_s": self.makespan, "cells_per_s": cells / max(self.makespan, 1e-12),
-                "iterations": self.iterations, "max_active": self.max_active,
+                "iterations": self.iterations, "passes": self.passes,
+                "max_active": self.max_active,
                 "max_resident_gb": self.max_resident_bytes / 1e9}
 
 
@@ -87,11 +89,16 @@ class ContinuousBatcher:
     def __init__(self, executor, cap_bytes: int, steps_per_pass: int,
                  keep_outputs: bool = False, clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep,
-                 max_cells_per_pass: Optional[int] = None):
-        """max_cells_per_pass: optional budget of cell updates per iteration;
+                 max_cells_per_pass: Optional[int] = None,
+                 horizon_cells: Optional[int] = None):
+        """max_cells_per_pass: optional budget of cell updates per pass;
         resident requests join a pass in admission order until it is spent
         (at least one always runs), so earlier requests finish first while
-        small ones still share passes."""
+        small ones still share passes.
+
+        horizon_cells: passes are queued back to back, without waiting for
+        the device, until a request finishes, a new request arrives, or this
+        many cell updates are queued (None: one pass per iteration)."""
         self.ex = executor
         self.cap = cap_bytes
         self.T = steps_per_pass
@@ -99,6 +106,7 @@ class ContinuousBatcher:
         self.clock = clock
         self.sleep = sleep
         self.budget = max_cells_per_pass
+        self.horizon = horizon_cells
 
     def serve(self, requests: Sequence[Request]) -> ServeStats:
         """Serve `requests` (arrival times in seconds after the start)."""
@@ -137,23 +145,34 @@ class ContinuousBatcher:
                     if wait > 0:
                         self.sleep(min(wait, 0.001))
                 continue
-            # one batched pass over the resident requests (in admission order,
-            # within the optional budget)
-            work, spent = [], 0
-            for s in active:
-                k = min(self.T, s.remaining)
-                cost = (3 ** s.req.r) * k
-                if work and self.budget is not None and spent + cost > self.budget:
-                    k = 0
-                spent += cost if k else 0
-                work.append((s.handle, k))
-            self.ex.run_pass(work)
+            # batched passes over the resident requests (in admission order,
+            # within the optional budget), queued back to back up to the horizon
+            queued = 0
+            while True:
+                work, spent = [], 0
+                for s in active:
+                    k = min(self.T, s.remaining)
+                    cost = (3 ** s.req.r) * k
+                    if work and self.budget is not None and spent + cost > self.budget:
+                        k = 0
+                    spent += cost if k else 0
+                    work.append((s.handle, k))
+                self.ex.run_pass(work)
+                st.passes += 1
+                finished = False
+                for s, (_, k) in zip(active, work):
+                    s.remaining -= k
+                    finished |= s.remaining == 0
+                queued += spent
+                if finished or self.horizon is None or queued >= self.horizon:
+                    break
+                if i < len(pending) and pending[i].arrival <= self.clock() - t0:
+                    break
             self.ex.sync()
             st.iterations += 1
             now = self.clock() - t0
             still = []
-            for s, (_, k) in zip(active, work):
-                s.remaining -= k
+            for s in active:
                 if s.remaining > 0:
                     still.append(s)
                     continue
@@ -182,6 +201,21 @@ class GpuExecutor:
         # (passes never write there), which is all a destination needs
         self.pool: Dict[int, List[object]] = {}
 
+    def reserve(self, levels: Sequence[int], cap_bytes: int) -> int:
+        """Pre-allocate the buffer pool, as a server sizes its memory at start:
+        two buffers per entry of `levels` (in order) while the total stays
+        under `cap_bytes`.  Returns the bytes reserved."""
+        total = 0
+        for r in levels:
+            fp = footprint(r)
+            if total + fp > cap_bytes:
+                break
+            n = 1 << r
+            self.pool.setdefault(r, []).extend(
+                self.torch.zeros((n, n), dtype=self.torch.uint8, device="cuda") for _ in range(2))
+            total += fp
+        return total
+
     def _buffer(self, r: int):
         free = self.pool.get(r)
         if free:
@@ -190,21 +224,24 @@ class GpuExecutor:
         return self.torch.zeros((n, n), dtype=self.torch.uint8, device="cuda")
 
     def admit(self, q: Request):
+        from .batch import checked_ptr
         cur = self._buffer(q.r)
         if q.template is not None:
             cur.copy_(self.templates[q.template])
         else:
             cur.copy_(self.torch.from_numpy(np.ascontiguousarray(q.state)))
-        return {"r": q.r, "buf": [cur, self._buffer(q.r)]}
+        nxt = self._buffer(q.r)
+        return {"r": q.r, "buf": [cur, nxt],
+                "p": [checked_ptr(cur, q.r, "state"), checked_ptr(nxt, q.r, "state")]}
 
     def run_pass(self, work):
-        items = []
-        for h, k in work:
-            items.append((h["buf"][0], h["buf"][1], h["r"], k))
-        self.ctx.run(items, self.tune)
+        from .batch import PASS_ITEM
+        items = np.array([(h["p"][0], h["p"][1], h["r"], k) for h, k in work], dtype=PASS_ITEM)
+        self.ctx.run_array(items, self.tune)
         for h, k in work:
             if k > 0:
                 h["buf"].reverse()
+                h["p"].reverse()
 
     def sync(self):
         self.torch.cuda.synchronize()

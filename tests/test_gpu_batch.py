@@ -138,8 +138,10 @@ def test_pass_context_mixed_steps():
     ctx.close()
 
 
-def test_serving_results_equal_alone_and_respect_the_cap():
-    note("continuous batching: 40 requests r=6..10")
+@pytest.mark.parametrize("horizon,budget", [(None, None), (3 ** 10 * 64, None),
+                                            (10 ** 12, 3 ** 9 * 8)])
+def test_serving_results_equal_alone_and_respect_the_cap(horizon, budget):
+    note(f"continuous batching: 40 requests r=6..10, horizon {horizon}, budget {budget}")
     rng = np.random.default_rng(21)
     reqs = []
     for i in range(40):
@@ -149,7 +151,8 @@ def test_serving_results_equal_alone_and_respect_the_cap():
                             inputs.bernoulli_state(r, 0.5, 500 + i)))
     cap = 6 * footprint(10)
     ex = GpuExecutor(B.make_tune(64, 8, 2, 256), capacity=64)
-    st = ContinuousBatcher(ex, cap_bytes=cap, steps_per_pass=8, keep_outputs=True).serve(reqs)
+    st = ContinuousBatcher(ex, cap_bytes=cap, steps_per_pass=8, keep_outputs=True,
+                           max_cells_per_pass=budget, horizon_cells=horizon).serve(reqs)
     ex.close()
     assert st.max_resident_bytes <= cap and st.max_active >= 2
     assert len(st.results) == 40 and not any(x.rejected for x in st.results)

@@ -118,3 +118,27 @@ def test_budgeted_passes_keep_results_and_order():
         assert np.array_equal(res.output, O.life_steps(q.r, q.state, q.steps))
     # every pass stays within the budget unless a single request exceeds it
     assert all(sum(1 for k in p if k) >= 1 for p in ex.passes if any(p))
+
+
+@pytest.mark.parametrize("horizon", [1, 3 ** 6 * 8, 10 ** 12])
+def test_queued_passes_keep_results(horizon):
+    reqs = _requests(30, 11, r_lo=4, r_hi=7, steps_hi=60)
+    clock = FakeClock()
+    ex = OracleExecutor()
+    st = ContinuousBatcher(ex, cap_bytes=10 ** 9, steps_per_pass=4, keep_outputs=True,
+                           clock=clock, sleep=clock.sleep, horizon_cells=horizon).serve(reqs)
+    assert len(st.results) == len(reqs)
+    for res in st.results:
+        q = reqs[res.rid]
+        assert np.array_equal(res.output, O.life_steps(q.r, q.state, q.steps))
+    assert st.passes == len(ex.passes) and st.iterations <= st.passes
+
+
+def test_a_lone_request_runs_all_its_passes_in_one_round():
+    q = Request(0, 0.0, 6, 37, inputs.bernoulli_state(6, 0.5, 3))
+    clock = FakeClock()
+    ex = OracleExecutor()
+    st = ContinuousBatcher(ex, cap_bytes=10 ** 9, steps_per_pass=8, keep_outputs=True,
+                           clock=clock, sleep=clock.sleep, horizon_cells=10 ** 12).serve([q])
+    assert st.iterations == 1 and st.passes == 5
+    assert np.array_equal(st.results[0].output, O.life_steps(6, q.state, 37))
