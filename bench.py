@@ -170,21 +170,28 @@ def bench_diffusion(torch, sg, inputs, rhos, steps, warmup):
             res[map_kind][rho] = ms
             log(f"diffuse r=14 {map_kind:6s} rho={rho:3d}: {ms * 1e3:8.2f} us/step")
             del bufs
-    # temporally blocked: 8 steps per pass at rho = 64, over `steps` steps
-    tb = {}
+    # temporally blocked: 4 or 8 steps per pass at rho = 32 and 64, over `steps` steps
+    tb = {"lambda": {}, "bbox": {}}
     Out, Work = torch.zeros_like(U), torch.zeros_like(U)
     for map_kind in ("lambda", "bbox"):
-        def run():
-            sg.sg_diffuse_steps(map_kind, r, 64, steps, U, Out, Work, 0.2, steps_per_pass=8)
-        tb[map_kind] = time_region(torch, run, 1, 1) / steps
-        log(f"diffuse r=14 {map_kind:6s} rho= 64 8/pass: {tb[map_kind] * 1e3:8.2f} us/step")
-    cands = [((rho, 1), ms) for rho, ms in res["lambda"].items()] + [((64, 8), tb["lambda"])]
+        for rho in (32, 64):
+            for T in (4, 8):
+                def run():
+                    sg.sg_diffuse_steps(map_kind, r, rho, steps, U, Out, Work, 0.2, steps_per_pass=T)
+                tb[map_kind][(rho, T)] = time_region(torch, run, 1, 1) / steps
+                log(f"diffuse r=14 {map_kind:6s} rho={rho:3d} {T}/pass: "
+                    f"{tb[map_kind][(rho, T)] * 1e3:8.2f} us/step")
+    cands = [((rho, 1), ms) for rho, ms in res["lambda"].items()] + list(tb["lambda"].items())
     (best, best_T), ms = min(cands, key=lambda kv: kv[1])
+    bb_cands = [((rho, 1), ms) for rho, ms in res["bbox"].items()] + list(tb["bbox"].items())
+    _, bb_ms = min(bb_cands, key=lambda kv: kv[1])
     return {"r": r, "cells": cells,
             "one_launch_per_step_us": {m: {str(k): round(v * 1e3, 2) for k, v in res[m].items()}
                                        for m in res},
-            "rho64_8_per_pass_us": {m: round(v * 1e3, 2) for m, v in tb.items()},
+            "temporally_blocked_us": {m: {f"rho{k[0]}_T{k[1]}": round(v * 1e3, 2)
+                                          for k, v in tb[m].items()} for m in tb},
             "best": {"rho": best, "steps_per_launch": best_T}, "cells_per_s": cells / (ms * 1e-3),
+            "best_vs_best_bbox": round(bb_ms / ms, 3),
             "hbm_frac_algorithmic": round(8 * cells / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
 
 

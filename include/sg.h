@@ -158,9 +158,11 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
 
 /* One explicit diffusion step on the gasket in FP32 (a nearest-neighbour
  * application, Section I): for every gasket cell,
- *   out = u + alpha * sum_{nb in W, E, N, S; in grid and in gasket} (u_nb - u),
- * summed in the order W, E, N, S; cells off the gasket are 0 and never
- * enter a sum.
+ *   out = u + alpha * sum_{nb in W, E, N, S; in grid and in gasket} (u_nb - u);
+ * cells off the gasket are 0 and never enter a sum.  In FP32 the sum is
+ * formed as (u_W + u_E) + (u_N + u_S) - deg * u (one fma; deg the number of
+ * those neighbours, off-gasket neighbours contributing their 0) and
+ * out = u + alpha * that (one fma).
  * d_in, d_out: device, n * n floats, distinct, not overlapping.
  * Errors: SG_EINVAL, SG_EALIAS. */
 SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in,
@@ -171,8 +173,8 @@ SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in,
  * of that many cells from HBM once and runs the steps on chip (temporal
  * blocking).  Every cell update is the same FP32 arithmetic as
  * sg_diffuse_step, so the result equals `steps` calls of it bit for bit.
- *   steps_per_pass: 1 (one launch per step, any rho), 2..8 (rho = 64), or 0
- *     for the library's choice (8 where supported, else 1).
+ *   steps_per_pass: 1 (one launch per step, any rho), 2..8 (rho in {32, 64}),
+ *     or 0 for the library's choice (8 where supported, else 1).
  *   d_in: read only.  d_out: the state after `steps` steps.  d_work: a third
  *     n * n float buffer, used when more than one pass runs (may be NULL
  *     otherwise).  All: device, 16-byte aligned, pairwise non-overlapping,

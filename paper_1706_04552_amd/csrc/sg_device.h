@@ -218,19 +218,23 @@ __device__ __forceinline__ uint32_t row_mask_word(int k, uint32_t ty) {
   return m;
 }
 
-// One explicit diffusion update of a cell (FP32): the neighbour differences
-// are summed in the order W, E, N, S, those whose neighbour is off the grid
-// or off the gasket skipped; a cell off the gasket is 0.  Every diffusion
-// kernel goes through this function, so they agree bit for bit.
+// One explicit diffusion update of a cell (FP32): with deg the number of the
+// cell's in-grid gasket neighbours, u + alpha * sum_nb (u_nb - u) is taken as
+//   t = (w + e) + (nn + ss) - deg * u   (one fma),   out = u + alpha * t,
+// which relies on every neighbour off the grid or off the gasket holding 0
+// (the state invariant); a cell off the gasket is 0.  Every diffusion kernel
+// goes through this function with its neighbours' values and deg, so they
+// agree bit for bit.
+__device__ __forceinline__ float diffuse_cell(float u, float w, float e, float nn, float ss,
+                                              float deg, bool self, float alpha) {
+  const float t = __builtin_fmaf(-deg, u, (w + e) + (nn + ss));
+  return self ? __builtin_fmaf(alpha, t, u) : 0.0f;
+}
 __device__ __forceinline__ float diffuse_cell(float u, float w, float e, float nn, float ss,
                                               bool mw, bool me, bool mn, bool ms, bool self,
                                               float alpha) {
-  float s = 0.0f;
-  s += mw ? (w - u) : 0.0f;
-  s += me ? (e - u) : 0.0f;
-  s += mn ? (nn - u) : 0.0f;
-  s += ms ? (ss - u) : 0.0f;
-  return self ? __builtin_fmaf(alpha, s, u) : 0.0f;
+  return diffuse_cell(u, w, e, nn, ss, (float)((int)mw + (int)me + (int)mn + (int)ms), self,
+                      alpha);
 }
 
 }  // namespace sg
