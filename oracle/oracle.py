@@ -47,6 +47,11 @@ def _load():
         "sgo_diffuse_step": (None, [_int, _ptr, _ptr, ctypes.c_double]),
         "sgo_diffuse_window": (None, [_int, _ptr, _i64, _i64, _i64, _i64, _int,
                                       ctypes.c_double, _ptr]),
+        "sgo_frac_member": (_int, [_int, _int, _ptr, _ptr, _int, _i64, _i64]),
+        "sgo_frac_lambda": (None, [_int, _int, _ptr, _ptr, _int, _i64, _i64, _ptr, _ptr]),
+        "sgo_frac_map": (None, [_int, _int, _ptr, _ptr, _int, _ptr]),
+        "sgo_frac_write": (None, [_int, _int, _ptr, _ptr, _int, ctypes.c_uint8, _ptr]),
+        "sgo_frac_life_step": (None, [_int, _int, _ptr, _ptr, _int, _ptr, _ptr]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -200,3 +205,63 @@ def diffuse_window(r: int, u0: np.ndarray, x0: int, y0: int, w: int, h: int,
     out = np.zeros((h, w), dtype=np.float64)
     _load().sgo_diffuse_window(r, _p(u0), x0, y0, w, h, steps, alpha, _p(out))
     return out
+
+
+# ---------------------------------------------------------------- other fractals F^{k,1/m}
+
+class Fractal:
+    """k kept sub-squares of an m x m subdivision, at offsets (dx[i], dy[i])
+    listed in the order the map's digit enumerates them (build frame)."""
+
+    def __init__(self, m: int, offsets):
+        self.m = int(m)
+        self.offsets = [(int(a), int(b)) for a, b in offsets]
+        self.k = len(self.offsets)
+        self._dx = np.array([a for a, _ in self.offsets], dtype=np.int32)
+        self._dy = np.array([b for _, b in self.offsets], dtype=np.int32)
+
+    def args(self):
+        return (self.m, self.k, _p(self._dx), _p(self._dy))
+
+    def n(self, r: int) -> int:
+        return self.m ** r
+
+
+GASKET = Fractal(2, [(0, 1), (0, 0), (1, 0)])  # beta = 0, 1, 2 after the build-frame reflection
+CARPET = Fractal(3, [(x, y) for y in range(3) for x in range(3) if (x, y) != (1, 1)])
+VICSEK = Fractal(3, [(1, 0), (0, 1), (1, 1), (2, 1), (1, 2)])
+
+
+def frac_member(f: Fractal, r: int, x: int, y: int) -> bool:
+    return bool(_load().sgo_frac_member(*f.args(), r, x, y))
+
+
+def frac_lambda(f: Fractal, rb: int, wx: int, wy: int):
+    lx, ly = ctypes.c_int64(), ctypes.c_int64()
+    _load().sgo_frac_lambda(*f.args(), rb, wx, wy, ctypes.byref(lx), ctypes.byref(ly))
+    return lx.value, ly.value
+
+
+def frac_map(f: Fractal, rb: int) -> np.ndarray:
+    """Rows (bx, by) of the generalised map, linear index wy * W + wx."""
+    out = np.zeros((f.k ** rb, 2), dtype=np.uint32)
+    _load().sgo_frac_map(*f.args(), rb, _p(out))
+    return out
+
+
+def frac_write(f: Fractal, r: int, value: int) -> np.ndarray:
+    n = f.n(r)
+    a = np.zeros((n, n), dtype=np.uint8)
+    _load().sgo_frac_write(*f.args(), r, value, _p(a))
+    return a
+
+
+def frac_life_steps(f: Fractal, r: int, a: np.ndarray, steps: int) -> np.ndarray:
+    n = f.n(r)
+    assert a.shape == (n, n) and a.dtype == np.uint8
+    cur = np.ascontiguousarray(a).copy()
+    nxt = np.zeros_like(cur)
+    for _ in range(steps):
+        _load().sgo_frac_life_step(*f.args(), r, _p(cur), _p(nxt))
+        cur, nxt = nxt, cur
+    return cur

@@ -357,6 +357,123 @@ void sgo_diffuse_window(int r, const float *in, int64_t x0, int64_t y0,
     free(b);
 }
 
+/* ------------------------------------------------------------------ */
+/* other embedded fractals F^{k,s} (Section III-A; Section V)          */
+/* ------------------------------------------------------------------ */
+
+/* A fractal built by replicating k copies of itself at scale s = 1/m
+ * (Section III-A): the m x m sub-squares kept at every scale are given by a
+ * motif, sub-square i at offset (fdx[i], fdy[i]) in [0, m)^2, all distinct,
+ * listed in the order the map's digit enumerates them.  n = m^r.  A cell
+ * (x, y) belongs to the level-r fractal iff at every scale the pair of its
+ * base-m digits is a kept offset.  The gasket is m = 2, k = 3 with the
+ * offsets {(0,0), (1,0), (0,1)} (build frame). */
+
+static int64_t ipow(int64_t b, int e)
+{
+    int64_t v = 1;
+    while (e-- > 0) v *= b;
+    return v;
+}
+
+static int sgo_frac_kept(int m, int k, const int *fdx, const int *fdy, int64_t dx, int64_t dy)
+{
+    (void)m;
+    for (int i = 0; i < k; ++i)
+        if (fdx[i] == dx && fdy[i] == dy) return 1;
+    return 0;
+}
+
+/* Membership by digits.  Pinned by: brute-force recursive construction,
+ * cell count k^r, the gasket motif against (x & y) == 0, the carpet against
+ * its textbook definition. */
+int sgo_frac_member(int m, int k, const int *fdx, const int *fdy, int r, int64_t x, int64_t y)
+{
+    for (int j = 0; j < r; ++j) {
+        if (!sgo_frac_kept(m, k, fdx, fdy, x % m, y % m)) return 0;
+        x /= m;
+        y /= m;
+    }
+    return 1;
+}
+
+/* The generalised block map: the W x H grid W = k^floor(rb/2),
+ * H = k^ceil(rb/2) (Eq. 4 with 3 replaced by k); at scale level mu the
+ * helper function beta_mu is the base-k digit of omega_y (odd mu) or
+ * omega_x (even mu) of weight k^(ceil(mu/2)-1) (Eq. 4), the offset
+ * function is the motif entry (Delta^x, Delta^y) = motif[beta_mu] (Eq. 5)
+ * and the weight function is m^(mu-1) (Eq. 6-7):
+ * lambda = sum_mu Delta_mu m^(mu-1) (Eq. 8-10).  Build frame (the motif is
+ * given in it, so no reflection).  Pinned by: the gasket motif reproduces
+ * sgo_map_lambda; exhaustive bijection onto the fractal blocks. */
+void sgo_frac_lambda(int m, int k, const int *fdx, const int *fdy, int rb, int64_t wx,
+                     int64_t wy, int64_t *lx, int64_t *ly)
+{
+    int64_t sx = 0, sy = 0;
+    for (int mu = 1; mu <= rb; ++mu) {
+        int64_t v = (mu % 2) ? wy : wx;
+        int64_t b = (v / ipow(k, (mu + 1) / 2 - 1)) % k;
+        int64_t off = ipow(m, mu - 1);
+        sx += fdx[b] * off;
+        sy += fdy[b] * off;
+    }
+    *lx = sx;
+    *ly = sy;
+}
+
+/* Table of the generalised map: out[2i], out[2i+1] = (bx, by) of the block
+ * at linear index i = wy * W + wx. */
+void sgo_frac_map(int m, int k, const int *fdx, const int *fdy, int rb, uint32_t *out)
+{
+    int64_t W = ipow(k, rb / 2), H = ipow(k, rb - rb / 2);
+    for (int64_t wy = 0; wy < H; ++wy)
+        for (int64_t wx = 0; wx < W; ++wx) {
+            int64_t lx, ly, i = wy * W + wx;
+            sgo_frac_lambda(m, k, fdx, fdy, rb, wx, wy, &lx, &ly);
+            out[2 * i] = (uint32_t)lx;
+            out[2 * i + 1] = (uint32_t)ly;
+        }
+}
+
+/* a[y][x] = value on the fractal's cells, 0 elsewhere (n = m^r). */
+void sgo_frac_write(int m, int k, const int *fdx, const int *fdy, int r, uint8_t value,
+                    uint8_t *a)
+{
+    int64_t n = ipow(m, r);
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < n; ++y)
+        for (int64_t x = 0; x < n; ++x)
+            a[y * n + x] = sgo_frac_member(m, k, fdx, fdy, r, x, y) ? value : 0;
+}
+
+/* One B3/S23 step on the fractal: neighbours are the 8-neighbourhood cells in
+ * the grid and in the fractal; cells off the fractal stay 0.  Pinned by the
+ * gasket motif against sgo_life_step and an independent neighbour-list
+ * formulation. */
+void sgo_frac_life_step(int m, int k, const int *fdx, const int *fdy, int r, const uint8_t *in,
+                        uint8_t *out)
+{
+    int64_t n = ipow(m, r);
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < n; ++y)
+        for (int64_t x = 0; x < n; ++x) {
+            if (!sgo_frac_member(m, k, fdx, fdy, r, x, y)) {
+                out[y * n + x] = 0;
+                continue;
+            }
+            int c = 0;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int64_t xx = x + dx, yy = y + dy;
+                    if ((dx || dy) && xx >= 0 && xx < n && yy >= 0 && yy < n &&
+                        sgo_frac_member(m, k, fdx, fdy, r, xx, yy))
+                        c += in[yy * n + xx] != 0;
+                }
+            int self = in[y * n + x] != 0;
+            out[y * n + x] = (uint8_t)(c == 3 || (self && c == 2));
+        }
+}
+
 /* Number of threads the OpenMP row loops above use. */
 #ifdef _OPENMP
 #include <omp.h>

@@ -358,3 +358,99 @@ def test_inputs_are_zero_off_the_gasket_and_seeded():
     m = recursive_gasket(r)
     draws = np.random.default_rng(3).random(3 ** r) < 0.3
     assert np.array_equal(inputs.bernoulli_state(r, 0.3, 3)[m], draws.astype(np.uint8))
+
+
+# ------------------------------------------------------------------ other fractals F^{k,1/m}
+
+FRACTALS = {"gasket": O.GASKET, "carpet": O.CARPET, "vicsek": O.VICSEK}
+
+
+def replicated(f, r: int) -> np.ndarray:
+    """The fractal's mask by its construction (Section III-A): level r+1 is k
+    copies of level r, copy i placed at sub-square (dx_i, dy_i) of an m x m
+    subdivision."""
+    mask = np.ones((1, 1), dtype=bool)
+    for _ in range(r):
+        n = mask.shape[0]
+        big = np.zeros((f.m * n, f.m * n), dtype=bool)
+        for dx, dy in f.offsets:
+            big[dy * n:(dy + 1) * n, dx * n:(dx + 1) * n] = mask
+        mask = big
+    return mask
+
+
+def frac_neighbour_list_life(mask: np.ndarray, a: np.ndarray) -> np.ndarray:
+    """B3/S23 on the cells of `mask` from an explicit neighbour list."""
+    h, w = mask.shape
+    out = np.zeros_like(a)
+    for (y, x) in zip(*np.nonzero(mask)):
+        c = 0
+        for dy, dx in itertools.product((-1, 0, 1), repeat=2):
+            yy, xx = y + dy, x + dx
+            if (dy or dx) and 0 <= yy < h and 0 <= xx < w and mask[yy, xx]:
+                c += int(a[yy, xx])
+        out[y, x] = 1 if (c == 3 or (a[y, x] and c == 2)) else 0
+    return out
+
+
+@pytest.mark.parametrize("name,rmax", [("gasket", 7), ("carpet", 4), ("vicsek", 4)])
+def test_fractal_membership_is_the_replication(name, rmax):
+    f = FRACTALS[name]
+    for r in range(rmax + 1):
+        a = O.frac_write(f, r, 1)
+        mask = replicated(f, r)
+        assert np.array_equal(a.astype(bool), mask)
+        assert int(a.sum()) == f.k ** r  # V(F) = k^r
+
+
+def test_gasket_motif_is_the_gasket():
+    for r in range(8):
+        assert np.array_equal(O.frac_write(O.GASKET, r, 5), O.write_pass(r, 5))
+
+
+def test_carpet_is_the_textbook_carpet():
+    # a cell is removed iff some base-3 digit position holds 1 in both x and y
+    r = 4
+    n = 3 ** r
+    y, x = np.mgrid[0:n, 0:n]
+    keep = np.ones((n, n), dtype=bool)
+    for _ in range(r):
+        keep &= ~((x % 3 == 1) & (y % 3 == 1))
+        x, y = x // 3, y // 3
+    assert np.array_equal(O.frac_write(O.CARPET, r, 1).astype(bool), keep)
+
+
+@pytest.mark.parametrize("rb", range(0, 9))
+def test_generalised_map_with_the_gasket_motif_is_lambda(rb):
+    assert np.array_equal(O.frac_map(O.GASKET, rb), O.map_lambda(rb))
+
+
+@pytest.mark.parametrize("name,rbmax", [("carpet", 4), ("vicsek", 5)])
+def test_generalised_map_is_a_bijection_onto_the_fractal_blocks(name, rbmax):
+    f = FRACTALS[name]
+    for rb in range(rbmax + 1):
+        tab = O.frac_map(f, rb)
+        assert len(tab) == f.k ** rb
+        got = {(int(bx), int(by)) for bx, by in tab}
+        assert len(got) == len(tab)
+        mask = replicated(f, rb)
+        assert got == {(int(x), int(y)) for y, x in zip(*np.nonzero(mask))}
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_gasket_motif_life_is_gasket_life(seed):
+    r = 6
+    a = inputs.bernoulli_state(r, 0.5, seed)
+    assert np.array_equal(O.frac_life_steps(O.GASKET, r, a, 7), O.life_steps(r, a, 7))
+
+
+@pytest.mark.parametrize("name,r", [("carpet", 3), ("vicsek", 3)])
+def test_fractal_life_matches_neighbour_list(name, r):
+    f = FRACTALS[name]
+    mask = replicated(f, r)
+    rng = np.random.default_rng(5)
+    a = ((rng.random(mask.shape) < 0.5) & mask).astype(np.uint8)
+    for _ in range(4):
+        b = O.frac_life_steps(f, r, a, 1)
+        assert np.array_equal(b, frac_neighbour_list_life(mask, a))
+        a = b
