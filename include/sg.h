@@ -213,6 +213,53 @@ SG_API int sg_ca_steps_compact(int r, int rho, int steps, int steps_per_pass,
                                void *stream);
 
 /* ---------------------------------------------------------------------
+ * Other embedded fractals F^{k,s}, s = 1/m (Section III-A), with the block
+ * map generalised to them (Section V): the fractal keeps k of the m x m
+ * sub-squares at every scale.  n = m^r, blocks of rho = m^q cells a side,
+ * r_b = r - q.  The generalised map launches k^r_b blocks: the W x H grid
+ * W = k^floor(r_b/2), H = k^ceil(r_b/2), the helper function beta_mu the
+ * base-k digit of omega_y (odd mu) or omega_x (even mu) of weight
+ * k^(ceil(mu/2)-1) (Eq. 4 with k for 3), the offset function the motif
+ * entry of beta_mu (for Eq. 5) and the weight m^(mu-1) (Eq. 6-10); with
+ * m = 2, k = 3 and the gasket's motif {(0,1), (0,0), (1,0)} it is lambda.
+ * The bounding box launches all (n/rho)^2 blocks and keeps the fractal ones.
+ * States: n x n uint8, row-major, 0 off the fractal (no alignment needed).
+ * --------------------------------------------------------------------- */
+#define SG_FRAC_MAX_M 4
+#define SG_FRAC_MAX_K 16
+#define SG_FRAC_MAX_N (1u << 18) /* largest n = m^r */
+#define SG_FRAC_MAX_RHO 243      /* largest block side */
+
+typedef struct sg_fractal {
+    int32_t m;                   /* subdivision, 2..SG_FRAC_MAX_M */
+    int32_t k;                   /* kept sub-squares, 1..min(m*m, SG_FRAC_MAX_K) */
+    uint8_t dx[SG_FRAC_MAX_K];   /* offsets of the kept sub-squares in [0, m), */
+    uint8_t dy[SG_FRAC_MAX_K];   /* distinct, in the order the digit enumerates them */
+} sg_fractal;
+
+/* Host only.  Blocks the map launches: k^r_b (SG_MAP_LAMBDA) or (n/rho)^2
+ * (SG_MAP_BBOX).  Errors: SG_EINVAL (bad motif, n > SG_FRAC_MAX_N, rho not a
+ * power of m up to n and SG_FRAC_MAX_RHO, k^r_b >= 2^32). */
+SG_API int sg_frac_block_count(const sg_fractal *f, int map, int r, int rho, uint64_t *blocks);
+
+/* Table of the generalised map: d_bxy[2i], d_bxy[2i+1] = (bx, by) of the
+ * block with linear index i = omega_y * W + omega_x.  d_bxy: device,
+ * 2 k^r_b uint32, 8-byte aligned.  Errors: SG_EINVAL (also k^r_b >= 2^31). */
+SG_API int sg_frac_map(const sg_fractal *f, int r, int rho, uint32_t *d_bxy, void *stream);
+
+/* The write pass on the fractal: `value` on its cells, 0 on the other cells
+ * of its blocks; blocks without a fractal cell are untouched.
+ * Errors: SG_EINVAL, SG_EHIP. */
+SG_API int sg_frac_write(const sg_fractal *f, int map, int r, int rho, uint8_t *d_a,
+                         uint8_t value, void *stream);
+
+/* One B3/S23 step on the fractal: neighbours are the 8-neighbourhood cells
+ * in the grid and on the fractal; cells off the fractal stay 0.  d_in, d_out:
+ * device, n * n, distinct.  Errors: SG_EINVAL, SG_EALIAS, SG_EHIP. */
+SG_API int sg_frac_life_step(const sg_fractal *f, int map, int r, int rho,
+                             const uint8_t *d_in, uint8_t *d_out, void *stream);
+
+/* ---------------------------------------------------------------------
  * Many gaskets at once (a batch of independent embedded gaskets of uneven
  * levels).  Every entry point below runs the temporally blocked life pass of
  * sg_ca_steps over the lambda tiles of all gaskets in one persistent launch

@@ -52,6 +52,8 @@ def _load():
         "sgo_frac_map": (None, [_int, _int, _ptr, _ptr, _int, _ptr]),
         "sgo_frac_write": (None, [_int, _int, _ptr, _ptr, _int, ctypes.c_uint8, _ptr]),
         "sgo_frac_life_step": (None, [_int, _int, _ptr, _ptr, _int, _ptr, _ptr]),
+        "sgo_frac_life_window": (None, [_int, _int, _ptr, _ptr, _int, _ptr, _i64, _i64, _i64,
+                                        _i64, _int, _ptr]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -265,3 +267,14 @@ def frac_life_steps(f: Fractal, r: int, a: np.ndarray, steps: int) -> np.ndarray
         _load().sgo_frac_life_step(*f.args(), r, _p(cur), _p(nxt))
         cur, nxt = nxt, cur
     return cur
+
+
+def frac_life_window(f: Fractal, r: int, a: np.ndarray, x0: int, y0: int, w: int, h: int,
+                     steps: int) -> np.ndarray:
+    """State after `steps` fractal life steps on the window [x0, x0+w) x [y0, y0+h)."""
+    n = f.n(r)
+    a = np.ascontiguousarray(a)
+    assert a.shape == (n, n) and a.dtype == np.uint8
+    out = np.zeros((h, w), dtype=np.uint8)
+    _load().sgo_frac_life_window(*f.args(), r, _p(a), x0, y0, w, h, steps, _p(out))
+    return out

@@ -474,6 +474,56 @@ void sgo_frac_life_step(int m, int k, const int *fdx, const int *fdy, int r, con
         }
 }
 
+/* `steps` fractal life steps on the window [x0, x0+w) x [y0, y0+h) of a full
+ * n x n state, from the window grown by `steps` cells on every side (clipped
+ * to the grid): a cell after t steps depends only on cells within Chebyshev
+ * distance t, and the wrong values at the region's cut edges travel inward
+ * one cell per step.  Membership is taken at the cells' global coordinates.
+ * Pinned by equality with full runs. */
+void sgo_frac_life_window(int m, int k, const int *fdx, const int *fdy, int r,
+                          const uint8_t *in, int64_t x0, int64_t y0, int64_t w, int64_t h,
+                          int steps, uint8_t *out)
+{
+    int64_t n = ipow(m, r);
+    int64_t gx0 = x0 - steps < 0 ? 0 : x0 - steps, gy0 = y0 - steps < 0 ? 0 : y0 - steps;
+    int64_t gx1 = x0 + w + steps > n ? n : x0 + w + steps;
+    int64_t gy1 = y0 + h + steps > n ? n : y0 + h + steps;
+    int64_t gw = gx1 - gx0, gh = gy1 - gy0;
+    uint8_t *a = (uint8_t *)malloc((size_t)(gw * gh));
+    uint8_t *b = (uint8_t *)malloc((size_t)(gw * gh));
+    for (int64_t y = 0; y < gh; ++y)
+        for (int64_t x = 0; x < gw; ++x)
+            a[y * gw + x] = in[(gy0 + y) * n + (gx0 + x)];
+    for (int s = 0; s < steps; ++s) {
+        for (int64_t y = 0; y < gh; ++y)
+            for (int64_t x = 0; x < gw; ++x) {
+                int64_t X = gx0 + x, Y = gy0 + y;
+                if (!sgo_frac_member(m, k, fdx, fdy, r, X, Y)) {
+                    b[y * gw + x] = 0;
+                    continue;
+                }
+                int c = 0;
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int64_t xx = x + dx, yy = y + dy;
+                        if ((dx || dy) && xx >= 0 && xx < gw && yy >= 0 && yy < gh &&
+                            sgo_frac_member(m, k, fdx, fdy, r, gx0 + xx, gy0 + yy))
+                            c += a[yy * gw + xx] != 0;
+                    }
+                int self = a[y * gw + x] != 0;
+                b[y * gw + x] = (uint8_t)(c == 3 || (self && c == 2));
+            }
+        uint8_t *t = a;
+        a = b;
+        b = t;
+    }
+    for (int64_t y = 0; y < h; ++y)
+        for (int64_t x = 0; x < w; ++x)
+            out[y * w + x] = a[(y0 - gy0 + y) * gw + (x0 - gx0 + x)];
+    free(a);
+    free(b);
+}
+
 /* Number of threads the OpenMP row loops above use. */
 #ifdef _OPENMP
 #include <omp.h>

@@ -63,6 +63,7 @@ int pass_args(int map, int r, int rho, void *stream, sg::PassArgs &a) {
 }  // namespace
 
 namespace sg {
+int status_of(hipError_t e) { return hip_status(e); }
 bool inject_hip_error() {
   static const bool on = getenv("SG_INJECT_HIP_ERROR") != nullptr;
   return on;

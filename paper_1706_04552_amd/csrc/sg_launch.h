@@ -12,6 +12,9 @@ namespace sg {
 // failure (SG_EHIP) instead, after validating its arguments.
 bool inject_hip_error();
 
+// SG_OK, or SG_EHIP with the HIP error's text kept for sg_last_hip_error.
+int status_of(hipError_t e);
+
 // One pass over the tiles of a map.
 struct PassArgs {
   int r;            // level: n = 2^r

@@ -56,6 +56,36 @@ def uniform_field(r: int, seed: int = DEFAULT_SEED) -> np.ndarray:
     return u
 
 
+def fractal_mask(m: int, offsets, r: int) -> np.ndarray:
+    """Boolean m^r x m^r mask of a fractal that keeps the m x m sub-squares at
+    `offsets` [(dx, dy), ...] at every scale (the domain of the other-fractal
+    workloads), built by placing copies of the previous level."""
+    mask = np.ones((1, 1), dtype=bool)
+    for _ in range(r):
+        n = mask.shape[0]
+        big = np.zeros((m * n, m * n), dtype=bool)
+        for dx, dy in offsets:
+            big[dy * n:(dy + 1) * n, dx * n:(dx + 1) * n] = mask
+        mask = big
+    return mask
+
+
+def fractal_state(m: int, offsets, r: int, p: float = 0.5,
+                  seed: int = DEFAULT_SEED) -> np.ndarray:
+    """uint8 state on a fractal: Bernoulli(p) 0/1 on its cells (one draw per
+    cell, row-major), 0 elsewhere."""
+    mask = fractal_mask(m, offsets, r)
+    n = mask.shape[0]
+    rng = np.random.default_rng(seed)
+    a = np.zeros((n, n), dtype=np.uint8)
+    step = _row_chunk(n)
+    for y0 in range(0, n, step):
+        y1 = min(n, y0 + step)
+        mk = mask[y0:y1]
+        a[y0:y1][mk] = (rng.random(int(mk.sum())) < p).astype(np.uint8)
+    return a
+
+
 @dataclass
 class InstanceSpec:
     """One gasket of a batch: level r, Bernoulli p, state seed."""

@@ -39,6 +39,23 @@ class sg_pass_item(ctypes.Structure):
                 ("r", ctypes.c_int32), ("steps", ctypes.c_int32)]
 
 
+SG_FRAC_MAX_K = 16
+
+
+class sg_fractal(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("dx", ctypes.c_uint8 * SG_FRAC_MAX_K), ("dy", ctypes.c_uint8 * SG_FRAC_MAX_K)]
+
+
+def fractal(m: int, offsets) -> sg_fractal:
+    """A fractal keeping the m x m sub-squares at `offsets` [(dx, dy), ...]."""
+    f = sg_fractal()
+    f.m, f.k = m, len(offsets)
+    for i, (a, b) in enumerate(offsets):
+        f.dx[i], f.dy[i] = a, b
+    return f
+
+
 # Every symbol declared in include/sg.h, with its ctypes signature.
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _vp = ctypes.c_void_p
@@ -75,6 +92,15 @@ _SIGNATURES = {
     "sg_ca_steps_compact": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]),
+    "sg_frac_block_count": (ctypes.c_int, [ctypes.POINTER(sg_fractal), ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, _u64p]),
+    "sg_frac_map": (ctypes.c_int, [ctypes.POINTER(sg_fractal), ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "sg_frac_write": (ctypes.c_int, [ctypes.POINTER(sg_fractal), ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, ctypes.c_void_p, ctypes.c_uint8, ctypes.c_void_p]),
+    "sg_frac_life_step": (ctypes.c_int, [ctypes.POINTER(sg_fractal), ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
     "sg_tune_default": (ctypes.c_int, [_tunep]),
     "sg_batch_create": (ctypes.c_int, [ctypes.POINTER(sg_gasket), ctypes.c_int, _tunep,
                                        ctypes.POINTER(_vp)]),
@@ -298,4 +324,40 @@ def sg_ca_steps_compact(r: int, rho: int, steps: int, d_in: torch.Tensor, d_out:
     pw = _dev(d_work, torch.uint8, size, "d_work") if d_work is not None else None
     _check(load().sg_ca_steps_compact(r, rho, steps, steps_per_pass, pi, po, pw, _stream(stream)),
            "sg_ca_steps_compact")
+    return d_out
+
+
+def sg_frac_block_count(f: sg_fractal, map_kind, r: int, rho: int) -> int:
+    b = ctypes.c_uint64()
+    _check(load().sg_frac_block_count(ctypes.byref(f), _map(map_kind), r, rho, ctypes.byref(b)),
+           "sg_frac_block_count")
+    return b.value
+
+
+def _frac_n2(f: sg_fractal, r: int) -> int:
+    return (f.m ** r) ** 2
+
+
+def sg_frac_map(f: sg_fractal, r: int, rho: int, d_bxy: torch.Tensor, stream=None) -> torch.Tensor:
+    """d_bxy: int32 CUDA tensor of 2 k^r_b elements (bx, by pairs)."""
+    count = sg_frac_block_count(f, "lambda", r, rho)
+    p = _dev(d_bxy, torch.int32, 2 * count, "d_bxy")
+    _check(load().sg_frac_map(ctypes.byref(f), r, rho, p, _stream(stream)), "sg_frac_map")
+    return d_bxy
+
+
+def sg_frac_write(f: sg_fractal, map_kind, r: int, rho: int, d_a: torch.Tensor, value: int,
+                  stream=None) -> torch.Tensor:
+    p = _dev(d_a, torch.uint8, _frac_n2(f, r), "d_a")
+    _check(load().sg_frac_write(ctypes.byref(f), _map(map_kind), r, rho, p, value, _stream(stream)),
+           "sg_frac_write")
+    return d_a
+
+
+def sg_frac_life_step(f: sg_fractal, map_kind, r: int, rho: int, d_in: torch.Tensor,
+                      d_out: torch.Tensor, stream=None) -> torch.Tensor:
+    pi = _dev(d_in, torch.uint8, _frac_n2(f, r), "d_in")
+    po = _dev(d_out, torch.uint8, _frac_n2(f, r), "d_out")
+    _check(load().sg_frac_life_step(ctypes.byref(f), _map(map_kind), r, rho, pi, po,
+                                    _stream(stream)), "sg_frac_life_step")
     return d_out

@@ -277,3 +277,35 @@ def test_compact_storage_validation(lib):
     assert lib.sg_map_lambda_inverse(r, rho, None, None) == sg.SG_EINVAL
     assert lib.sg_map_lambda_inverse(r, rho, ctypes.c_void_p(0x100002), None) == sg.SG_EINVAL
     assert lib.sg_map_lambda_inverse(20, 1, ctypes.c_void_p(0x100000), None) == sg.SG_EINVAL
+
+
+def test_fractal_validation(lib):
+    from paper_1706_04552_amd import sg
+    carpet = sg.fractal(3, [(x, y) for y in range(3) for x in range(3) if (x, y) != (1, 1)])
+    b = ctypes.c_uint64()
+    assert lib.sg_frac_block_count(ctypes.byref(carpet), 0, 5, 9, ctypes.byref(b)) == sg.SG_OK
+    assert b.value == 8 ** 3
+    assert lib.sg_frac_block_count(ctypes.byref(carpet), 1, 5, 9, ctypes.byref(b)) == sg.SG_OK
+    assert b.value == 27 ** 2
+    assert lib.sg_frac_block_count(ctypes.byref(carpet), 0, 5, 1, ctypes.byref(b)) == sg.SG_OK
+    assert b.value == 8 ** 5
+    # rho must be a power of m within n; n within the limit; map kind valid
+    for r, rho, m in ((5, 4, 0), (5, 2, 0), (2, 27, 0), (12, 3, 0), (5, 9, 2), (6, 729, 0)):
+        assert lib.sg_frac_block_count(ctypes.byref(carpet), m, r, rho, ctypes.byref(b)) == sg.SG_EINVAL
+    assert lib.sg_frac_block_count(None, 0, 5, 9, ctypes.byref(b)) == sg.SG_EINVAL
+    assert lib.sg_frac_block_count(ctypes.byref(carpet), 0, 5, 9, None) == sg.SG_EINVAL
+    # bad motifs: offset out of range, repeated offset, too many, m out of range
+    for m, offs in ((3, [(3, 0)]), (3, [(0, 0), (0, 0)]), (2, [(0, 0)] * 5), (5, [(0, 0)]),
+                    (1, [(0, 0)])):
+        f = sg.fractal(max(m, 2), offs[:16]) if m >= 2 else sg.fractal(2, offs)
+        f.m = m
+        assert lib.sg_frac_block_count(ctypes.byref(f), 0, 2, 1, ctypes.byref(b)) == sg.SG_EINVAL
+    empty = sg.fractal(3, [])
+    assert lib.sg_frac_block_count(ctypes.byref(empty), 0, 2, 1, ctypes.byref(b)) == sg.SG_EINVAL
+    a, c = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x7000000000)
+    assert lib.sg_frac_write(ctypes.byref(carpet), 0, 5, 9, None, 1, None) == sg.SG_EINVAL
+    assert lib.sg_frac_life_step(ctypes.byref(carpet), 0, 5, 9, a, None, None) == sg.SG_EINVAL
+    assert lib.sg_frac_life_step(ctypes.byref(carpet), 0, 5, 9, a,
+                                 ctypes.c_void_p(0x100000 + 243 * 243 - 1), None) == sg.SG_EALIAS
+    assert lib.sg_frac_map(ctypes.byref(carpet), 5, 9, ctypes.c_void_p(0x100004), None) == sg.SG_EINVAL
+    assert lib.sg_frac_map(ctypes.byref(carpet), 5, 9, None, None) == sg.SG_EINVAL

@@ -1,0 +1,126 @@
+"""GPU parity for other embedded fractals F^{k,1/m}: the generalised block map
+and the write and life passes through the C ABI against the CPU oracle, for
+the carpet (m = 3, k = 8), the Vicsek fractal (m = 3, k = 5) and the gasket's
+motif (m = 2, k = 3).  Bit-exact at every size; the full-size life run is
+checked on sampled windows and by the two maps agreeing."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_1706_04552_amd import inputs, sg
+
+pytestmark = pytest.mark.gpu
+
+ORACLE = {"carpet": O.CARPET, "vicsek": O.VICSEK, "gasket": O.GASKET}
+
+
+def note(msg):
+    print(f"[case] {msg}", file=sys.stderr, flush=True)
+
+
+def lib_fractal(name):
+    f = ORACLE[name]
+    return sg.fractal(f.m, f.offsets)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    sg.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def cases(name, rs):
+    m = ORACLE[name].m
+    out = []
+    for r in rs:
+        q = 0
+        while m ** q <= min(m ** r, 243):
+            out.append((name, r, m ** q))
+            q += 1
+    return out
+
+
+ALL = (cases("carpet", [0, 1, 3, 5]) + cases("vicsek", [2, 5]) + cases("gasket", [4, 9]))
+
+
+@pytest.mark.parametrize("name,r,rho", ALL)
+def test_frac_map_exact(name, r, rho):
+    note(f"frac_map {name} r={r} rho={rho}")
+    f = lib_fractal(name)
+    q = round(np.log(rho) / np.log(f.m))
+    ref = O.frac_map(ORACLE[name], r - q).astype(np.int64)
+    got = torch.zeros(2 * len(ref), dtype=torch.int32, device="cuda")
+    sg.sg_frac_map(f, r, rho, got)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().reshape(-1, 2).astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
+@pytest.mark.parametrize("name,r,rho", ALL)
+def test_frac_write_exact(map_kind, name, r, rho):
+    note(f"frac_write {map_kind} {name} r={r} rho={rho}")
+    f = lib_fractal(name)
+    n = f.m ** r
+    a = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+    sg.sg_frac_write(f, map_kind, r, rho, a, 7)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.cpu().numpy(), O.frac_write(ORACLE[name], r, 7))
+
+
+def gpu_frac_life(f, map_kind, r, rho, a0, steps):
+    a = torch.from_numpy(np.ascontiguousarray(a0)).cuda()
+    b = torch.zeros_like(a)
+    for _ in range(steps):
+        sg.sg_frac_life_step(f, map_kind, r, rho, a, b)
+        a, b = b, a
+    torch.cuda.synchronize()
+    return a
+
+
+@pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
+@pytest.mark.parametrize("name,r,rho", cases("carpet", [1, 4, 5]) + cases("vicsek", [5])
+                         + cases("gasket", [3, 8]))
+def test_frac_life_exact(map_kind, name, r, rho):
+    note(f"frac_life {map_kind} {name} r={r} rho={rho} 6 steps")
+    of = ORACLE[name]
+    a0 = inputs.fractal_state(of.m, of.offsets, r, 0.5, 40 + r)
+    got = gpu_frac_life(lib_fractal(name), map_kind, r, rho, a0, 6).cpu().numpy()
+    assert np.array_equal(got, O.frac_life_steps(of, r, a0, 6))
+
+
+def test_frac_life_gasket_motif_equals_gasket_kernels():
+    r, rho, steps = 10, 16, 5
+    note(f"frac_life gasket motif vs gasket life r={r}")
+    a0 = inputs.bernoulli_state(r, 0.5, 77)
+    got = gpu_frac_life(lib_fractal("gasket"), "lambda", r, rho, a0, steps)
+    a = torch.from_numpy(a0).cuda()
+    out, work = torch.zeros_like(a), torch.zeros_like(a)
+    sg.sg_ca_steps("lambda", r, rho, steps, a, out, work, steps_per_pass=1)
+    torch.cuda.synchronize()
+    assert torch.equal(got, out)
+
+
+@pytest.mark.parametrize("name,rho", [("carpet", 27), ("vicsek", 81)])
+def test_frac_life_full_size_sampled(name, rho):
+    r, steps = 9, 6
+    note(f"frac_life full-size {name} r={r} rho={rho} {steps} steps")
+    of = ORACLE[name]
+    a0 = inputs.fractal_state(of.m, of.offsets, r, 0.5, 1706)
+    f = lib_fractal(name)
+    lam = gpu_frac_life(f, "lambda", r, rho, a0, steps)
+    box = gpu_frac_life(f, "bbox", r, rho, a0, steps)
+    assert torch.equal(lam, box)
+    got = lam.cpu().numpy()
+    n = of.n(r)
+    mask = inputs.fractal_mask(of.m, of.offsets, r)
+    assert not got[~mask].any() and got.max() <= 1
+    rng = np.random.default_rng(3)
+    for _ in range(4):
+        x0, y0 = int(rng.integers(0, n - 40)), int(rng.integers(0, n - 20))
+        ref = O.frac_life_window(of, r, a0, x0, y0, 40, 20, steps)
+        assert np.array_equal(got[y0:y0 + 20, x0:x0 + 40], ref), (x0, y0)

@@ -454,3 +454,22 @@ def test_fractal_life_matches_neighbour_list(name, r):
         b = O.frac_life_steps(f, r, a, 1)
         assert np.array_equal(b, frac_neighbour_list_life(mask, a))
         a = b
+
+
+@pytest.mark.parametrize("name,r,steps", [("carpet", 4, 3), ("vicsek", 4, 5), ("gasket", 6, 4)])
+def test_fractal_life_window_equals_full_run(name, r, steps):
+    f = FRACTALS[name]
+    a = inputs.fractal_state(f.m, f.offsets, r, 0.5, 9)
+    full = O.frac_life_steps(f, r, a, steps)
+    n = f.n(r)
+    for (x0, y0, w, h) in ((0, 0, 5, 4), (n - 7, n - 3, 7, 3), (n // 3, n // 2, 9, 6)):
+        assert np.array_equal(O.frac_life_window(f, r, a, x0, y0, w, h, steps),
+                              full[y0:y0 + h, x0:x0 + w])
+
+
+def test_fractal_state_is_zero_off_the_fractal_and_seeded():
+    f = O.CARPET
+    a = inputs.fractal_state(f.m, f.offsets, 4, 0.5, 3)
+    assert np.array_equal(a, inputs.fractal_state(f.m, f.offsets, 4, 0.5, 3))
+    assert not a[~replicated(f, 4)].any()
+    assert 0.4 < a[replicated(f, 4)].mean() < 0.6
