@@ -230,6 +230,58 @@ def bench_batched(torch, sg, inputs, count, steps, runs):
     return out
 
 
+def bench_fractals(torch, sg, r, steps):
+    """Other embedded fractals at r = 10 (n = 59049, a 3.5 GB uint8 embedding):
+    the write pass and the life step, generalised block map against the
+    bounding box, at every block side 3^q.  The life state is Bernoulli(0.5)
+    on the fractal's cells, drawn on the device (torch generator, seed 1706)."""
+    motifs = {"carpet": (3, [(x, y) for y in range(3) for x in range(3) if (x, y) != (1, 1)]),
+              "vicsek": (3, [(1, 0), (0, 1), (1, 1), (2, 1), (1, 2)])}
+    out = {}
+    for name, (m, offs) in motifs.items():
+        f = sg.fractal(m, offs)
+        n = m ** r
+        cells = len(offs) ** r
+        A = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+        sg.sg_frac_write(f, "lambda", r, 1, A, 1)  # the fractal's mask
+        g = torch.Generator(device="cuda")
+        g.manual_seed(SEED)
+        step_rows = max(1, (1 << 28) // n)
+        for y0 in range(0, n, step_rows):
+            rows = A[y0:y0 + step_rows]
+            rows &= (torch.rand(rows.shape, generator=g, device="cuda") < 0.5).to(torch.uint8)
+        B = torch.zeros_like(A)
+        W = torch.zeros_like(A)
+        res = {"n": n, "cells": cells, "write_us": {}, "life_us": {}}
+        rho = 3
+        while rho <= 243:
+            for map_kind in ("lambda", "bbox"):
+                wt = time_region(torch, lambda: sg.sg_frac_write(f, map_kind, r, rho, W, 1), steps, 2)
+                bufs, st = [A.clone(), B], {"i": 0}
+
+                def life():
+                    i = st["i"]
+                    sg.sg_frac_life_step(f, map_kind, r, rho, bufs[i], bufs[1 - i])
+                    st["i"] = 1 - i
+                lt = time_region(torch, life, steps, 2)
+                res["write_us"].setdefault(map_kind, {})[str(rho)] = round(wt * 1e3, 2)
+                res["life_us"].setdefault(map_kind, {})[str(rho)] = round(lt * 1e3, 2)
+                del bufs
+            log(f"{name} r={r} rho={rho:3d}: write lambda {res['write_us']['lambda'][str(rho)]:9.1f} us "
+                f"bbox {res['write_us']['bbox'][str(rho)]:9.1f} us; life lambda "
+                f"{res['life_us']['lambda'][str(rho)]:9.1f} us bbox {res['life_us']['bbox'][str(rho)]:9.1f} us")
+            rho *= 3
+        for kind in ("write_us", "life_us"):
+            lam = min(res[kind]["lambda"].values())
+            box = min(res[kind]["bbox"].values())
+            res[kind.replace("_us", "_best_vs_best")] = round(box / lam, 3)
+        res["life_cells_per_s"] = cells / (min(res["life_us"]["lambda"].values()) * 1e-6)
+        out[name] = res
+        del A, B, W
+        torch.cuda.empty_cache()
+    return out
+
+
 def bench_serving(torch, sg, inputs, qps_list, count, cap_gb, horizon_cells=None,
                   budget_cells=None):
     """Poisson arrivals of life solves (r ~ U{8..15}, steps ~ U{10..200}) served
@@ -446,6 +498,8 @@ def main():
                                                           (4, 8, 16, 32, 64, 128, 256), 100)
         extras["diffusion"] = bench_diffusion(torch, sg, inputs, (16, 64, 128, 256), args.steps, args.warmup)
         extras["batched"] = bench_batched(torch, sg, inputs, args.batch_count, 50, 5)
+        extras["other_fractals"] = bench_fractals(torch, sg, 10, 20)
+        torch.cuda.empty_cache()
         torch.cuda.empty_cache()
         extras["serving"] = bench_serving(torch, sg, inputs, args.serve_qps, args.serve_requests, 200.0,
                                           int(args.serve_horizon) or None,
