@@ -64,8 +64,8 @@ def traffic_from_profile(kernel_tag):
         rec = json.load(open(path))
     except ValueError:
         return None
-    from paper_1706_04552_amd.build import source_digest
-    if rec.get("source_digest") != source_digest():
+    from paper_1706_04552_amd.build import LIFE_TB_SOURCES, source_digest
+    if rec.get("source_digest") != source_digest(LIFE_TB_SOURCES):
         return None
     return rec.get("bytes_per_launch")
 

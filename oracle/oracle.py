@@ -47,6 +47,8 @@ def _load():
         "sgo_diffuse_step": (None, [_int, _ptr, _ptr, ctypes.c_double]),
         "sgo_diffuse_window": (None, [_int, _ptr, _i64, _i64, _i64, _i64, _int,
                                       ctypes.c_double, _ptr]),
+        "sgo_map_lambda_rect": (None, [_int, _int, _int, _ptr]),
+        "sgo_map_bbox_rect": (None, [_int, _int, _int, _ptr]),
         "sgo_frac_member": (_int, [_int, _int, _ptr, _ptr, _int, _i64, _i64]),
         "sgo_frac_lambda": (None, [_int, _int, _ptr, _ptr, _int, _i64, _i64, _ptr, _ptr]),
         "sgo_frac_map": (None, [_int, _int, _ptr, _ptr, _int, _ptr]),
@@ -126,6 +128,23 @@ def map_bbox(r: int, rho: int) -> np.ndarray:
     nb = (1 << r) // rho
     out = np.zeros((nb, nb), dtype=np.uint8)
     _load().sgo_map_bbox(r, rho, _p(out))
+    return out
+
+
+def map_lambda_rect(r: int, rho_x: int, rho_y: int) -> np.ndarray:
+    """Rows (bx, by) of the map onto rho_x x rho_y blocks (powers of two)."""
+    a, b = rho_x.bit_length() - 1, rho_y.bit_length() - 1
+    hi, d = max(a, b), abs(a - b)
+    out = np.zeros((3 ** (r - hi) * 2 ** d, 2), dtype=np.uint32)
+    _load().sgo_map_lambda_rect(r, a, b, _p(out))
+    return out
+
+
+def map_bbox_rect(r: int, rho_x: int, rho_y: int) -> np.ndarray:
+    """Bounding-box block mask, shape (n/rho_y, n/rho_x), indexed [by, bx]."""
+    n = 1 << r
+    out = np.zeros((n // rho_y, n // rho_x), dtype=np.uint8)
+    _load().sgo_map_bbox_rect(r, rho_x, rho_y, _p(out))
     return out
 
 

@@ -358,6 +358,56 @@ void sgo_diffuse_window(int r, const float *in, int64_t x0, int64_t y0,
 }
 
 /* ------------------------------------------------------------------ */
+/* rectangular blocks rho_x x rho_y (Section III-B)                    */
+/* ------------------------------------------------------------------ */
+
+/* Blocks of rho_x = 2^a columns by rho_y = 2^b rows.  For a >= b, a block
+ * (bx, by) holds a gasket cell iff bx & (by >> (a-b)) == 0: its columns' bits
+ * below a are free, so only the bits at and above a must be disjoint; the
+ * 2^(a-b) blocks stacked in one 2^a x 2^a square are all kept or all not.
+ * The map decodes the square block by lambda at level r - a (linear order
+ * omega_sq = wy * W + wx) and the position in the stack as the 2^(a-b)
+ * lowest values of omega: omega = omega_sq * 2^(a-b) + j, by = by_sq * 2^(a-b)
+ * + j.  For b > a the roles of x and y swap.  With a = b it is lambda.
+ * out[2i], out[2i+1] = (bx, by).  Pinned by: exhaustive bijection onto the
+ * blocks that hold gasket cells, the count 3^(r - max) 2^|a - b|, equality
+ * with sgo_map_lambda for a = b. */
+void sgo_map_lambda_rect(int r, int a, int b, uint32_t *out)
+{
+    int hi = a > b ? a : b, d = a > b ? a - b : b - a;
+    int rb = r - hi;
+    int64_t W, H, nb = (int64_t)1 << rb, stack = (int64_t)1 << d;
+    sgo_lambda_grid(rb, &W, &H);
+    for (int64_t wy = 0; wy < H; ++wy)
+        for (int64_t wx = 0; wx < W; ++wx) {
+            int64_t lx, ly, sq = wy * W + wx;
+            sgo_lambda(rb, wx, wy, &lx, &ly);
+            int64_t bx = lx, by = nb - 1 - ly;
+            for (int64_t j = 0; j < stack; ++j) {
+                int64_t i = sq * stack + j;
+                out[2 * i] = (uint32_t)(a >= b ? bx : bx * stack + j);
+                out[2 * i + 1] = (uint32_t)(a >= b ? by * stack + j : by);
+            }
+        }
+}
+
+/* mask[by * (n/rho_x) + bx] = 1 iff the rho_x x rho_y block holds a gasket
+ * cell, found by scanning its cells. */
+void sgo_map_bbox_rect(int r, int rho_x, int rho_y, uint8_t *mask)
+{
+    int64_t n = (int64_t)1 << r, nbx = n / rho_x, nby = n / rho_y;
+#pragma omp parallel for schedule(static)
+    for (int64_t by = 0; by < nby; ++by)
+        for (int64_t bx = 0; bx < nbx; ++bx) {
+            int keep = 0;
+            for (int64_t ty = 0; ty < rho_y; ++ty)
+                for (int64_t tx = 0; tx < rho_x; ++tx)
+                    keep |= sgo_member(bx * rho_x + tx, by * rho_y + ty);
+            mask[by * nbx + bx] = (uint8_t)keep;
+        }
+}
+
+/* ------------------------------------------------------------------ */
 /* other embedded fractals F^{k,s} (Section III-A; Section V)          */
 /* ------------------------------------------------------------------ */
 

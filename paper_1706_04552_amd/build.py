@@ -33,12 +33,22 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def source_digest() -> str:
-    """SHA-256 over the library's sources, used to tell whether a stored
-    profile still describes the current kernels."""
+# Sources that define the temporally blocked life pass (the kernel, its
+# device helpers, its launch bookkeeping and the compile flags in this file).
+LIFE_TB_SOURCES = ("sg_life_tb.hip", "sg_device.h", "sg_launch.h")
+
+
+def source_digest(names=None) -> str:
+    """SHA-256 over library sources (all of them, or the csrc files named),
+    plus the compile flags, used to tell whether a stored profile still
+    describes the current kernels."""
     import hashlib
     h = hashlib.sha256()
-    files = sorted(glob.glob(os.path.join(CSRC, "*")) + [os.path.join(ROOT, "include", "sg.h")])
+    h.update(" ".join(HIP_FLAGS).encode())
+    if names is None:
+        files = sorted(glob.glob(os.path.join(CSRC, "*")) + [os.path.join(ROOT, "include", "sg.h")])
+    else:
+        files = [os.path.join(CSRC, n) for n in sorted(names)]
     for f in files:
         h.update(os.path.basename(f).encode())
         with open(f, "rb") as fh:

@@ -473,3 +473,27 @@ def test_fractal_state_is_zero_off_the_fractal_and_seeded():
     assert np.array_equal(a, inputs.fractal_state(f.m, f.offsets, 4, 0.5, 3))
     assert not a[~replicated(f, 4)].any()
     assert 0.4 < a[replicated(f, 4)].mean() < 0.6
+
+
+# ------------------------------------------------------------------ rectangular blocks
+
+@pytest.mark.parametrize("r,rho_x,rho_y", [(6, 8, 2), (6, 2, 8), (7, 32, 4), (7, 4, 32), (5, 32, 1),
+                                           (5, 1, 32), (8, 16, 16), (9, 64, 4), (4, 16, 16)])
+def test_rect_map_is_a_bijection_onto_the_live_blocks(r, rho_x, rho_y):
+    tab = O.map_lambda_rect(r, rho_x, rho_y)
+    a, b = rho_x.bit_length() - 1, rho_y.bit_length() - 1
+    assert len(tab) == 3 ** (r - max(a, b)) * 2 ** abs(a - b)
+    got = {(int(x), int(y)) for x, y in tab}
+    assert len(got) == len(tab)
+    # the blocks that hold a gasket cell, from the cell-level mask (independent of the map)
+    mask = recursive_gasket(r)
+    n = 1 << r
+    live = mask.reshape(n // rho_y, rho_y, n // rho_x, rho_x).any(axis=(1, 3))
+    assert got == {(int(x), int(y)) for y, x in zip(*np.nonzero(live))}
+    assert np.array_equal(O.map_bbox_rect(r, rho_x, rho_y).astype(bool), live)
+
+
+@pytest.mark.parametrize("r,rho", [(6, 4), (8, 16), (5, 32)])
+def test_rect_map_with_square_blocks_is_lambda(r, rho):
+    rb = r - (rho.bit_length() - 1)
+    assert np.array_equal(O.map_lambda_rect(r, rho, rho), O.map_lambda(rb))
