@@ -471,6 +471,15 @@ def main():
                                  args.steps, args.warmup)
                 intra.setdefault(variant, {}).setdefault(map_kind, {})[str(rho)] = round(ms * 1e3, 3)
                 log(f"write {variant:6s} {map_kind:6s} rho={rho:3d}: {ms * 1e3:9.2f} us")
+    # rectangular blocks: whole 64-byte rows with fewer cells per block
+    rect = {}
+    for (rx, ry) in ((64, 4), (64, 16), (128, 8), (256, 4), (256, 16), (256, 64)):
+        for map_kind in ("lambda", "bbox"):
+            ms = time_region(torch, lambda: sg.sg_write_pass_rect(map_kind, R, rx, ry, Wt, 1),
+                             args.steps, args.warmup)
+            rect.setdefault(map_kind, {})[f"{rx}x{ry}"] = round(ms * 1e3, 3)
+        log(f"write rect {rx:3d}x{ry:<3d}: lambda {rect['lambda'][f'{rx}x{ry}']:9.2f} us  "
+            f"bbox {rect['bbox'][f'{rx}x{ry}']:9.2f} us")
     del Wt
     wl = min(wp["lambda"], key=lambda k: wp["lambda"][k])
     wb = min(wp["bbox"], key=lambda k: wp["bbox"][k])
@@ -553,6 +562,7 @@ def main():
             "best_vs_best": round(wp["bbox"][wb] / wp["lambda"][wl], 3),
             "best_rho": {"lambda": wl, "bbox": wb},
             "intra_block_variants_us": intra,
+            "rectangular_blocks_us": rect,
             "lambda_cells_per_s": cells / (wp["lambda"][wl] * 1e-3),
             "paper_context": PAPER_BEST_VS_BEST,
         },

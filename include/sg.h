@@ -213,6 +213,35 @@ SG_API int sg_ca_steps_compact(int r, int rho, int steps, int steps_per_pass,
                                void *stream);
 
 /* ---------------------------------------------------------------------
+ * Rectangular blocks (Section III-B defines blocks of rho_x x rho_y
+ * threads): rho_x = 2^a columns by rho_y = 2^b rows, powers of two up to
+ * SG_MAX_RHO and n.  For a >= b the blocks that hold a gasket cell are
+ * (bx, by) with bx & (by >> (a-b)) == 0 (for b > a, (bx >> (b-a)) & by == 0):
+ * 3^(r - max(a,b)) * 2^|a-b| of them, the 2^|a-b| blocks that tile one
+ * lambda square block of side 2^max(a,b).  The map decodes the square with
+ * lambda and takes the position in the stack from the lowest bits of the
+ * block index; with a = b it is sg_map_lambda.
+ * --------------------------------------------------------------------- */
+
+/* Host only.  Blocks launched: 3^(r-max(a,b)) * 2^|a-b| (SG_MAP_LAMBDA) or
+ * (n/rho_x) * (n/rho_y) (SG_MAP_BBOX).  Errors: SG_EINVAL. */
+SG_API int sg_block_count_rect(int map, int r, int rho_x, int rho_y, uint64_t *blocks);
+
+/* d_bxy[2i], d_bxy[2i+1] = (bx, by) of block i: i = omega * 2^|a-b| + j,
+ * omega lambda's linear index of the square block, j the position in its
+ * stack (downwards for a >= b, rightwards for b > a).  d_bxy: device,
+ * 8-byte aligned.  Errors: SG_EINVAL (also more than 2^31 - 1 blocks). */
+SG_API int sg_map_lambda_rect(int r, int rho_x, int rho_y, uint32_t *d_bxy, void *stream);
+
+/* The write pass (Section IV) over rho_x x rho_y blocks: `value` on every
+ * gasket cell; inside a kept block cells off the gasket may be written with
+ * 0 (16-byte chunks, or whole 64-byte granules for rho_x >= 64); blocks and
+ * granules without a gasket cell are untouched.  d_a: device, n * n,
+ * 16-byte aligned.  Errors: SG_EINVAL, SG_EHIP. */
+SG_API int sg_write_pass_rect(int map, int r, int rho_x, int rho_y, uint8_t *d_a,
+                              uint8_t value, void *stream);
+
+/* ---------------------------------------------------------------------
  * Other embedded fractals F^{k,s}, s = 1/m (Section III-A), with the block
  * map generalised to them (Section V): the fractal keeps k of the m x m
  * sub-squares at every scale.  n = m^r, blocks of rho = m^q cells a side,

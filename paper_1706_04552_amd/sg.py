@@ -92,6 +92,12 @@ _SIGNATURES = {
     "sg_ca_steps_compact": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p]),
+    "sg_block_count_rect": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           _u64p]),
+    "sg_map_lambda_rect": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
+    "sg_write_pass_rect": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_void_p, ctypes.c_uint8, ctypes.c_void_p]),
     "sg_frac_block_count": (ctypes.c_int, [ctypes.POINTER(sg_fractal), ctypes.c_int, ctypes.c_int,
                                            ctypes.c_int, _u64p]),
     "sg_frac_map": (ctypes.c_int, [ctypes.POINTER(sg_fractal), ctypes.c_int, ctypes.c_int,
@@ -361,3 +367,26 @@ def sg_frac_life_step(f: sg_fractal, map_kind, r: int, rho: int, d_in: torch.Ten
     _check(load().sg_frac_life_step(ctypes.byref(f), _map(map_kind), r, rho, pi, po,
                                     _stream(stream)), "sg_frac_life_step")
     return d_out
+
+
+def sg_block_count_rect(map_kind, r: int, rho_x: int, rho_y: int) -> int:
+    b = ctypes.c_uint64()
+    _check(load().sg_block_count_rect(_map(map_kind), r, rho_x, rho_y, ctypes.byref(b)),
+           "sg_block_count_rect")
+    return b.value
+
+
+def sg_map_lambda_rect(r: int, rho_x: int, rho_y: int, d_bxy: torch.Tensor,
+                       stream=None) -> torch.Tensor:
+    count = sg_block_count_rect("lambda", r, rho_x, rho_y)
+    p = _dev(d_bxy, torch.int32, 2 * count, "d_bxy")
+    _check(load().sg_map_lambda_rect(r, rho_x, rho_y, p, _stream(stream)), "sg_map_lambda_rect")
+    return d_bxy
+
+
+def sg_write_pass_rect(map_kind, r: int, rho_x: int, rho_y: int, d_a: torch.Tensor, value: int,
+                       stream=None) -> torch.Tensor:
+    p = _dev(d_a, torch.uint8, _n2(r), "d_a")
+    _check(load().sg_write_pass_rect(_map(map_kind), r, rho_x, rho_y, p, value, _stream(stream)),
+           "sg_write_pass_rect")
+    return d_a

@@ -309,3 +309,20 @@ def test_fractal_validation(lib):
                                  ctypes.c_void_p(0x100000 + 243 * 243 - 1), None) == sg.SG_EALIAS
     assert lib.sg_frac_map(ctypes.byref(carpet), 5, 9, ctypes.c_void_p(0x100004), None) == sg.SG_EINVAL
     assert lib.sg_frac_map(ctypes.byref(carpet), 5, 9, None, None) == sg.SG_EINVAL
+
+
+def test_rect_validation(lib):
+    from paper_1706_04552_amd import sg
+    b = ctypes.c_uint64()
+    assert lib.sg_block_count_rect(0, 10, 64, 4, ctypes.byref(b)) == sg.SG_OK
+    assert b.value == 3 ** 4 * 16
+    assert lib.sg_block_count_rect(1, 10, 64, 4, ctypes.byref(b)) == sg.SG_OK
+    assert b.value == 16 * 256
+    assert lib.sg_block_count_rect(0, 10, 4, 64, ctypes.byref(b)) == sg.SG_OK
+    assert b.value == 3 ** 4 * 16
+    for r, rx, ry in ((10, 48, 4), (10, 64, 3), (3, 16, 4), (10, 512, 4), (10, 0, 4), (21, 4, 4)):
+        assert lib.sg_block_count_rect(0, r, rx, ry, ctypes.byref(b)) == sg.SG_EINVAL
+    assert lib.sg_block_count_rect(2, 10, 4, 4, ctypes.byref(b)) == sg.SG_EINVAL
+    assert lib.sg_write_pass_rect(0, 10, 64, 4, ctypes.c_void_p(0x100008), 1, None) == sg.SG_EINVAL
+    assert lib.sg_write_pass_rect(0, 10, 64, 4, None, 1, None) == sg.SG_EINVAL
+    assert lib.sg_map_lambda_rect(10, 64, 4, ctypes.c_void_p(0x100004), None) == sg.SG_EINVAL

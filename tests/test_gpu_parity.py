@@ -402,3 +402,43 @@ def test_ca_steps_compact_full_size_equals_embedding():
     comp = gpu_ca_steps_compact(r, rho, a0, steps, 16)
     emb = gpu_ca_steps("lambda", r, rho, a0, steps, 16)
     assert torch.equal(comp, emb)
+
+
+# ------------------------------------------------------------------ rectangular blocks
+
+RECT = [(6, 8, 2), (6, 2, 8), (7, 32, 4), (7, 4, 32), (5, 32, 1), (5, 1, 32), (8, 16, 16),
+        (9, 64, 4), (10, 256, 16), (10, 16, 256), (12, 64, 1), (11, 128, 8), (4, 16, 16)]
+
+
+@pytest.mark.parametrize("r,rho_x,rho_y", RECT)
+def test_map_lambda_rect_exact(r, rho_x, rho_y):
+    note(f"map_lambda_rect r={r} {rho_x}x{rho_y}")
+    ref = O.map_lambda_rect(r, rho_x, rho_y).astype(np.int64)
+    got = torch.zeros(2 * len(ref), dtype=torch.int32, device="cuda")
+    sg.sg_map_lambda_rect(r, rho_x, rho_y, got)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy().reshape(-1, 2).astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
+@pytest.mark.parametrize("r,rho_x,rho_y", RECT)
+def test_write_pass_rect_exact(map_kind, r, rho_x, rho_y):
+    note(f"write_pass_rect {map_kind} r={r} {rho_x}x{rho_y}")
+    n = 1 << r
+    a = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+    sg.sg_write_pass_rect(map_kind, r, rho_x, rho_y, a, 9)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.cpu().numpy(), O.write_pass(r, 9))
+
+
+def test_write_pass_rect_full_size():
+    r = 16
+    note(f"write_pass_rect full size r={r} 256x16, both maps")
+    n = 1 << r
+    a = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+    sg.sg_write_pass_rect("lambda", r, 256, 16, a, 1)
+    b = torch.zeros_like(a)
+    sg.sg_write_pass("lambda", r, 64, b, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert int(a.sum(dtype=torch.int64)) == 3 ** r
