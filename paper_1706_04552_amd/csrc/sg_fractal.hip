@@ -118,11 +118,66 @@ struct FracPass {
   uint64_t ntiles;
 };
 
+// In-tile membership as bit rows: bit tx of word wd of row ty (tx = 32 wd +
+// bit) is set iff cell (tx, ty) of a fractal tile is on the fractal.  Built
+// once per workgroup from level masks: L[j][d] holds the columns whose level-j
+// digit forms a kept offset with row digit d, and row ty is the AND over the
+// levels j of L[j][digit_j(ty)] (membership is a product over levels).
+constexpr int kMaskWords = (SG_FRAC_MAX_RHO + 31) / 32;
+// Tiles at least this wide are written a word at a time (the bit rows pay for
+// themselves); smaller ones a cell at a time.
+constexpr uint32_t kWordTileMin = 64;
+
+template <int M>
+__device__ __forceinline__ void build_row_masks(const FracArgs &f, int q, uint32_t rho,
+                                                uint32_t *L, uint32_t *rows) {
+  const int nw = (int)(rho + 31) / 32;  // words a row needs
+  const int nl = q * M * nw;
+  for (int e = threadIdx.x; e < nl; e += kFracThreads) {
+    const int wd = e % nw, d = (e / nw) % M, j = e / (nw * M);
+    uint32_t div = 1;
+    for (int l = 0; l < j; ++l) div *= M;
+    uint32_t w = 0;
+    const int bits = (int)rho - 32 * wd < 32 ? (int)rho - 32 * wd : 32;
+    for (int b = 0; b < bits; ++b) {
+      const uint32_t dx = ((32u * wd + b) / div) % M;
+      w |= ((f.kept >> (dx + M * d)) & 1u) << b;
+    }
+    L[(j * M + d) * kMaskWords + wd] = w;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < (int)rho * kMaskWords; e += kFracThreads) {
+    const uint32_t ty = e / kMaskWords, wd = e - ty * kMaskWords;
+    if ((int)wd >= nw) {
+      rows[e] = 0u;
+      continue;
+    }
+    uint32_t w = ~0u, v = ty;
+    for (int j = 0; j < q; ++j) {
+      const uint32_t d = v % M;
+      v /= M;
+      w &= L[(j * M + d) * kMaskWords + wd];
+    }
+    rows[e] = w;
+  }
+}
+
+// Bits [b, b + 4) of a bit row (b may be negative or run past the row: those
+// bits read as 0).
+__device__ __forceinline__ uint32_t row_bits4(const uint32_t *row, int b) {
+  const int b0 = b + 32;  // the row is read with one zero word before it
+  const uint32_t wi = (uint32_t)b0 >> 5, sh = (uint32_t)b0 & 31u;
+  const uint32_t lo = wi >= 1 && wi <= (uint32_t)kMaskWords ? row[wi - 1] : 0u;
+  const uint32_t hi = wi + 1 >= 1 && wi < (uint32_t)kMaskWords ? row[wi] : 0u;
+  return __builtin_amdgcn_alignbit(hi, lo, sh) & 15u;
+}
+
+// Small tiles: one thread per cell, membership from the local digits.
 template <int M, bool LAMBDA>
-__global__ __launch_bounds__(kFracThreads) void k_frac_write(FracArgs f, FracPass p,
-                                                             uint64_t tile_base,
-                                                             uint8_t *__restrict__ a,
-                                                             uint32_t value) {
+__global__ __launch_bounds__(kFracThreads) void k_frac_write_cells(FracArgs f, FracPass p,
+                                                                   uint64_t tile_base,
+                                                                   uint8_t *__restrict__ a,
+                                                                   uint32_t value) {
   __shared__ uint32_t sbx[kFracThreads], sby[kFracThreads];
   __shared__ uint8_t sok[kFracThreads];
   const int tid = threadIdx.x;
@@ -141,6 +196,53 @@ __global__ __launch_bounds__(kFracThreads) void k_frac_write(FracArgs f, FracPas
     const uint32_t ty = c / p.rho, tx = c - ty * p.rho;
     const size_t y = (size_t)sby[s] * p.rho + ty, x = (size_t)sbx[s] * p.rho + tx;
     a[y * p.n + x] = kept_digits<M>(f, tx, ty, p.q) ? (uint8_t)value : (uint8_t)0;
+  }
+}
+
+// Tiles of kWordTileMin cells a side or more: one thread per 4-byte-aligned
+// word of a tile row: whole words are stored as
+// one 32-bit store, the words at the row's two ends byte by byte.
+template <int M, bool LAMBDA>
+__global__ __launch_bounds__(kFracThreads) void k_frac_write(FracArgs f, FracPass p,
+                                                             uint64_t tile_base,
+                                                             uint8_t *__restrict__ a,
+                                                             uint32_t value) {
+  __shared__ uint32_t sbx[kFracThreads], sby[kFracThreads];
+  __shared__ uint8_t sok[kFracThreads];
+  __shared__ uint32_t L[160];  // levels x m x words: at most 7 x 2, 5 x 3 or 3 x 4 x 8
+  __shared__ uint32_t rows[SG_FRAC_MAX_RHO * kMaskWords];
+  const int tid = threadIdx.x;
+  const uint64_t t0 = tile_base + (uint64_t)logical_group() * p.tpg;
+  if (tid < p.tpg) {
+    uint32_t bx = 0, by = 0;
+    sok[tid] = frac_tile<M, LAMBDA>(f, t0 + tid, p.ntiles, p.rb, p.nb, bx, by);
+    sbx[tid] = bx;
+    sby[tid] = by;
+  }
+  build_row_masks<M>(f, p.q, p.rho, L, rows);
+  __syncthreads();
+  const uint32_t wpr = (p.rho + 3) / 4 + 1;  // aligned words a tile row can touch
+  const uint32_t per_tile = p.rho * wpr;
+  for (uint32_t e = tid; e < (uint32_t)p.tpg * per_tile; e += kFracThreads) {
+    const uint32_t s = e / per_tile, c = e - s * per_tile;
+    if (!sok[s]) continue;
+    const uint32_t ty = c / wpr, k = c - ty * wpr;
+    const size_t y = (size_t)sby[s] * p.rho + ty;
+    uint8_t *row0 = a + y * p.n + (size_t)sbx[s] * p.rho;  // the tile row's first cell
+    // k-th 4-byte-aligned word touching the tile row, and the tile column of
+    // its first byte (-3..rho)
+    uint8_t *dst = reinterpret_cast<uint8_t *>(((uintptr_t)row0 & ~(uintptr_t)3) + 4 * k);
+    const int tx0 = (int)(dst - row0);
+    if (tx0 >= (int)p.rho) continue;
+    const uint32_t bits = row_bits4(rows + ty * kMaskWords, tx0);
+    const uint32_t bytes = ((bits * 0x00204081u) & 0x01010101u) * value;
+    if (tx0 >= 0 && tx0 + 4 <= (int)p.rho) {
+      *reinterpret_cast<uint32_t *>(dst) = bytes;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (tx0 + i >= 0 && tx0 + i < (int)p.rho) dst[i] = (uint8_t)(bytes >> (8 * i));
+    }
   }
 }
 
@@ -189,21 +291,121 @@ __global__ __launch_bounds__(kFracThreads) void k_frac_life(FracArgs f, FracPass
   }
 }
 
+// Life step on tiles of kWordTileMin cells a side or more (one tile per
+// workgroup): the tile and a one-cell halo are staged in LDS with every tile
+// row starting on a 4-byte boundary, then one thread takes 4 cells of a tile
+// row at a time as one LDS word (SWAR on bytes: 3-row column sums, neighbour
+// bytes by funnel shifts, B3/S23 as (count | self) == 3), masks them with the
+// in-tile membership bits and stores them.
+template <int M>
+__host__ __device__ constexpr uint32_t life_stride(uint32_t rho) {
+  return 4u + 4u * ((rho + 1u + 3u) / 4u) + 4u;  // left pad word, tile + right halo, one spare word
+}
+
+template <int M, bool LAMBDA>
+__global__ __launch_bounds__(kFracThreads) void k_frac_life_words(FracArgs f, FracPass p,
+                                                                  uint64_t tile_base,
+                                                                  const uint8_t *__restrict__ in,
+                                                                  uint8_t *__restrict__ out) {
+  extern __shared__ __align__(16) uint8_t reg[];  // (rho + 2) rows of life_stride bytes
+  __shared__ uint32_t L[160];
+  __shared__ uint32_t tile_xy[2];
+  __shared__ uint8_t tile_ok;
+  const int tid = threadIdx.x;
+  const uint64_t t = tile_base + logical_group();
+  if (tid == 0) {
+    uint32_t bx = 0, by = 0;
+    tile_ok = frac_tile<M, LAMBDA>(f, t, p.ntiles, p.rb, p.nb, bx, by);
+    tile_xy[0] = bx;
+    tile_xy[1] = by;
+  }
+  // level masks (the row masks are formed per word below)
+  const int nw = (int)(p.rho + 31) / 32;
+  for (int e = tid; e < p.q * M * nw; e += kFracThreads) {
+    const int wd = e % nw, d = (e / nw) % M, j = e / (nw * M);
+    uint32_t div = 1;
+    for (int l = 0; l < j; ++l) div *= M;
+    uint32_t w = 0;
+    const int bits = (int)p.rho - 32 * wd < 32 ? (int)p.rho - 32 * wd : 32;
+    for (int b = 0; b < bits; ++b) w |= ((f.kept >> (((32u * wd + b) / div) % M + M * d)) & 1u) << b;
+    L[(j * M + d) * kMaskWords + wd] = w;
+  }
+  __syncthreads();
+  if (!tile_ok) return;
+  const uint32_t S = life_stride<M>(p.rho), side = p.rho + 2;
+  const int64_t X0 = (int64_t)tile_xy[0] * p.rho, Y0 = (int64_t)tile_xy[1] * p.rho;
+  // region cell (i, j), j = tile column + 1, at byte i * S + 3 + j
+  for (uint32_t e = tid; e < side * S / 4; e += kFracThreads) reinterpret_cast<uint32_t *>(reg)[e] = 0u;
+  __syncthreads();
+  for (uint32_t e = tid; e < side * side; e += kFracThreads) {
+    const uint32_t i = e / side, j = e - i * side;
+    const int64_t y = Y0 + i - 1, x = X0 + j - 1;
+    if (y >= 0 && y < p.n && x >= 0 && x < p.n) {
+      const uint8_t v = in[(size_t)y * p.n + (size_t)x];
+      if (v) reg[i * S + 3 + j] = v;
+    }
+  }
+  __syncthreads();
+  const uint32_t wpr = (p.rho + 3) / 4;
+  for (uint32_t e = tid; e < p.rho * wpr; e += kFracThreads) {
+    const uint32_t ty = e / wpr, c = e - ty * wpr;
+    const uint32_t *r0 = reinterpret_cast<const uint32_t *>(reg + ty * S + 4) + c;  // row above
+    const uint32_t *r1 = reinterpret_cast<const uint32_t *>(reg + (ty + 1) * S + 4) + c;
+    const uint32_t *r2 = reinterpret_cast<const uint32_t *>(reg + (ty + 2) * S + 4) + c;
+    const uint32_t C = r1[0];
+    const uint32_t V = r0[0] + C + r2[0];
+    const uint32_t Vp = r0[-1] + r1[-1] + r2[-1];
+    const uint32_t Vn = r0[1] + r1[1] + r2[1];
+    const uint32_t Lb = __builtin_amdgcn_alignbit(V, Vp, 24);  // byte i <- column 4c + i - 1
+    const uint32_t Rb = __builtin_amdgcn_alignbit(Vn, V, 8);   // byte i <- column 4c + i + 1
+    const uint32_t cnt = Lb + V + Rb - C;                      // live neighbours, per byte
+    const uint32_t x = (cnt | C) ^ 0x03030303u;
+    uint32_t z = x | (x >> 1);
+    z |= z >> 2;
+    // membership of columns 4c..4c+3 of row ty: AND over levels of L[j][digit_j(ty)]
+    uint32_t m = ~0u, v = ty;
+    const uint32_t wd = (4 * c) >> 5;
+    for (int j = 0; j < p.q; ++j) {
+      const uint32_t d = v % M;
+      v /= M;
+      m &= L[(j * M + d) * kMaskWords + wd];
+    }
+    const uint32_t bits = (m >> ((4 * c) & 31u)) & 15u;
+    const uint32_t alive = ~z & ((bits * 0x00204081u) & 0x01010101u);
+    uint8_t *dst = out + (size_t)(Y0 + ty) * p.n + (size_t)(X0 + 4 * c);
+    const uint32_t ncell = p.rho - 4 * c < 4 ? p.rho - 4 * c : 4;
+    if (ncell == 4 && ((uintptr_t)dst & 3u) == 0) {
+      *reinterpret_cast<uint32_t *>(dst) = alive;
+    } else {
+      for (uint32_t b = 0; b < ncell; ++b) dst[b] = (uint8_t)(alive >> (8 * b));
+    }
+  }
+}
+
 constexpr uint64_t kFracMaxGroups = 1ull << 22;
 
 template <int M, bool LAMBDA, bool LIFE>
 hipError_t frac_pass_m(const FracArgs &f, const FracPass &p, hipStream_t s, uint8_t *a,
                        const uint8_t *in, uint32_t value) {
   const uint64_t groups = (p.ntiles + p.tpg - 1) / p.tpg;
-  const size_t lds = LIFE ? (size_t)p.tpg * (p.rho + 2) * (p.rho + 2) : 0;
+  const bool words = p.rho >= kWordTileMin;
+  const size_t lds = !LIFE ? 0
+                     : words ? (size_t)(p.rho + 2) * life_stride<M>(p.rho)
+                             : (size_t)p.tpg * (p.rho + 2) * (p.rho + 2);
   for (uint64_t g0 = 0; g0 < groups; g0 += kFracMaxGroups) {
     const uint64_t g = groups - g0 < kFracMaxGroups ? groups - g0 : kFracMaxGroups;
-    if (LIFE)
+    if (LIFE && words)
+      hipLaunchKernelGGL((k_frac_life_words<M, LAMBDA>), dim3((unsigned)g), dim3(kFracThreads),
+                         lds, s, f, p, g0 * (uint64_t)p.tpg, in, a);
+    else if (LIFE)
       hipLaunchKernelGGL((k_frac_life<M, LAMBDA>), dim3((unsigned)g), dim3(kFracThreads), lds, s,
                          f, p, g0 * (uint64_t)p.tpg, in, a);
-    else
+    else if (p.rho >= kWordTileMin)
       hipLaunchKernelGGL((k_frac_write<M, LAMBDA>), dim3((unsigned)g), dim3(kFracThreads), 0, s,
                          f, p, g0 * (uint64_t)p.tpg, a, value);
+    else
+      hipLaunchKernelGGL((k_frac_write_cells<M, LAMBDA>), dim3((unsigned)g), dim3(kFracThreads),
+                         0, s, f, p, g0 * (uint64_t)p.tpg, a, value);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
