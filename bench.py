@@ -330,6 +330,19 @@ def bench_serving(torch, sg, inputs, qps_list, count, cap_gb, horizon_cells=None
             ex.release(h)
             ex.pool[q.r].append(work)
         ex.close()
+        del ex
+        torch.cuda.empty_cache()
+        # the same policy in native code (sg_server_*): queue, pool and rounds
+        nat = serving.NativeServer(tune, int(cap_gb * 1e9), count, int(horizon_cells or 0),
+                                   int(budget_cells or 0))
+        nat.reserve([q.r for q in rq])
+        inits = {q.rid: templates[q.r] for q in rq}
+        serving.serve_native(nat, rq[:16], inits)  # warm-up
+        nsumm = serving.serve_native(nat, rq, inits).summary()
+        nat.close()
+        del nat
+        torch.cuda.empty_cache()
+        summ["native_server"] = nsumm
         lat, end = serving.sequential_baseline(svc, [q.arrival for q in rq])
         cells = float(sum(3 ** q.r * q.steps for q in rq))
         summ["one_at_a_time"] = {"p50_ms": float(np.percentile(lat, 50) * 1e3),
@@ -339,10 +352,10 @@ def bench_serving(torch, sg, inputs, qps_list, count, cap_gb, horizon_cells=None
         log(f"serving qps={qps:.0f}: p50 {summ['p50_ms']:.2f} ms p99 {summ['p99_ms']:.2f} ms "
             f"{summ['cells_per_s'] / 1e9:.1f} Gcells/s; one at a time p50 "
             f"{summ['one_at_a_time']['p50_ms']:.2f} p99 {summ['one_at_a_time']['p99_ms']:.2f} ms "
-            f"{summ['one_at_a_time']['cells_per_s'] / 1e9:.1f} Gcells/s")
+            f"{summ['one_at_a_time']['cells_per_s'] / 1e9:.1f} Gcells/s; native server p50 "
+            f"{nsumm['p50_ms']:.2f} p99 {nsumm['p99_ms']:.2f} ms "
+            f"{nsumm['cells_per_s'] / 1e9:.1f} Gcells/s")
         results.append(summ)
-        del ex
-        torch.cuda.empty_cache()
     return {"tune": tune.as_dict(), "requests": count, "horizon_cells": horizon_cells,
             "budget_cells": budget_cells, "by_qps": results}
 

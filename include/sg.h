@@ -384,6 +384,65 @@ SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
 /* Waits for the context's last upload and frees it (NULL is ignored). */
 SG_API void sg_pass_ctx_destroy(sg_pass_ctx *ctx);
 
+/* ---------------------------------------------------------------------
+ * Continuous batching of life solves (a native serving loop over
+ * sg_pass_run).  Requests are admitted first come first served while their
+ * footprint (two n x n buffers taken from a device pool that the server owns
+ * and recycles by level) fits under cap_bytes.  Every sg_server_step is one
+ * scheduling round: admission, then batched passes over every resident
+ * request (oldest first within budget_cells of cell updates per pass, if
+ * non-zero) queued without waiting for the device until a request finishes
+ * or horizon_cells updates are queued (0: one pass per round), then one wait
+ * and the retirement of finished requests.  One host thread per server.
+ * --------------------------------------------------------------------- */
+typedef struct sg_server sg_server;
+
+typedef struct sg_server_done {
+    uint64_t tag;            /* the tag given to sg_server_submit */
+    const uint8_t *result;   /* device n x n state after `steps` generations,
+                                valid until the next sg_server_step; NULL if
+                                rejected */
+    int32_t rejected;        /* 1: the footprint can never fit under the cap */
+} sg_server_done;
+
+typedef struct sg_server_stats {
+    uint64_t rounds, passes, completed, rejected, cell_steps;
+    uint64_t max_resident_bytes, max_active;
+    uint64_t queued, active, resident_bytes; /* now */
+} sg_server_stats;
+
+/* tune: the batched pass's launch shape (as sg_batch_create); max_requests:
+ * queued plus resident requests at most.  Errors: SG_EINVAL, SG_ENOMEM,
+ * SG_EHIP. */
+SG_API int sg_server_create(const sg_tune *tune, uint64_t cap_bytes, int max_requests,
+                            uint64_t horizon_cells, uint64_t budget_cells, void *stream,
+                            sg_server **out);
+
+/* Pre-allocates the pool as a server sizes its memory at start: two buffers
+ * per entry of `levels` (6..SG_MAX_R, host array), in order, while the pool
+ * stays under the cap.  Synchronises the stream.  Errors: SG_EINVAL,
+ * SG_ENOMEM, SG_EHIP. */
+SG_API int sg_server_reserve(sg_server *s, const int32_t *levels, int count);
+
+/* Queues a request: `steps` generations of the level-r gasket (r 6..SG_MAX_R)
+ * from d_init (device, n x n, 16-byte aligned, 0 off the gasket; read when
+ * the request is admitted, so it must stay valid until then).  d_out: NULL,
+ * or a device n x n buffer (16-byte aligned) that receives a copy of the
+ * result before the round that finishes the request returns.
+ * Errors: SG_EINVAL, SG_ENOMEM (max_requests reached). */
+SG_API int sg_server_submit(sg_server *s, int r, int steps, const uint8_t *d_init,
+                            uint8_t *d_out, uint64_t tag);
+
+/* One scheduling round; reports up to max_done finished (or rejected)
+ * requests in `done` (host array) and their number in *n_done.
+ * Errors: SG_EINVAL, SG_ENOMEM, SG_EHIP. */
+SG_API int sg_server_step(sg_server *s, sg_server_done *done, int max_done, int *n_done);
+
+SG_API int sg_server_get_stats(const sg_server *s, sg_server_stats *out);
+
+/* Waits for the stream, frees the pool (NULL is ignored). */
+SG_API void sg_server_destroy(sg_server *s);
+
 #ifdef __cplusplus
 }
 #endif

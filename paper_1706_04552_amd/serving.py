@@ -268,3 +268,102 @@ def sequential_baseline(service_times: Sequence[float], arrivals: Sequence[float
         finish = start + service_times[j]
         lat[j] = finish - arrivals[j]
     return lat, finish
+
+
+class NativeServer:
+    """The continuous-batching loop of libsg (sg_server_*): the same policy as
+    ContinuousBatcher -- FIFO admission by footprint, batched passes over every
+    resident request, oldest first within an optional budget, passes queued
+    until a request finishes or a horizon of cell updates -- with the queue,
+    the device buffer pool and the pass planning in native code."""
+
+    def __init__(self, tune, cap_bytes: int, max_requests: int, horizon_cells: int = 0,
+                 budget_cells: int = 0, stream=None):
+        import ctypes
+
+        import torch
+        from . import sg
+        self._sg = sg
+        self._ct = ctypes
+        self._u8 = torch.uint8
+        self._h = None
+        h = ctypes.c_void_p()
+        sg._check(sg.load().sg_server_create(ctypes.byref(tune), int(cap_bytes), int(max_requests),
+                                             int(horizon_cells), int(budget_cells),
+                                             sg._stream(stream), ctypes.byref(h)),
+                  "sg_server_create")
+        self._h = h
+        self._done = (sg.sg_server_done * max_requests)()
+        self.max_requests = max_requests
+
+    def reserve(self, levels: Sequence[int]):
+        arr = (self._ct.c_int32 * max(1, len(levels)))(*levels)
+        self._sg._check(self._sg.load().sg_server_reserve(self._h, arr, len(levels)),
+                        "sg_server_reserve")
+
+    def submit(self, r: int, steps: int, init, tag: int, out=None):
+        """init (and out, if given): uint8 n x n CUDA tensors kept alive by the caller."""
+        sg = self._sg
+        pi = sg._dev(init, self._u8, (1 << r) * (1 << r), "init")
+        po = sg._dev(out, self._u8, (1 << r) * (1 << r), "out") if out is not None else None
+        sg._check(sg.load().sg_server_submit(self._h, r, steps, pi, po, tag), "sg_server_submit")
+
+    def step(self):
+        """One scheduling round: [(tag, rejected), ...] of the requests it ended."""
+        n = self._ct.c_int()
+        self._sg._check(self._sg.load().sg_server_step(self._h, self._done, self.max_requests,
+                                                       self._ct.byref(n)), "sg_server_step")
+        return [(int(self._done[i].tag), bool(self._done[i].rejected)) for i in range(n.value)]
+
+    def stats(self) -> Dict[str, int]:
+        st = self._sg.sg_server_stats()
+        self._sg._check(self._sg.load().sg_server_get_stats(self._h, self._ct.byref(st)),
+                        "sg_server_get_stats")
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            self._sg.load().sg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def serve_native(server: NativeServer, requests: Sequence[Request], inits: Dict[int, object],
+                 outs: Optional[Dict[int, object]] = None,
+                 clock: Callable[[], float] = time.perf_counter) -> ServeStats:
+    """Drives `server` with requests arriving in real time (arrival seconds
+    after the start): each is submitted once its arrival time has passed, and
+    the server runs a round whenever it has work.  inits[rid] (and outs[rid],
+    if given) are the requests' device tensors."""
+    pending = sorted(requests, key=lambda q: (q.arrival, q.rid))
+    by_id = {q.rid: q for q in pending}
+    st = ServeStats()
+    s0 = server.stats()
+    t0 = clock()
+    i = 0
+    open_ids = set()
+    while i < len(pending) or open_ids:
+        now = clock() - t0
+        while i < len(pending) and pending[i].arrival <= now:
+            q = pending[i]
+            server.submit(q.r, q.steps, inits[q.rid], q.rid, outs.get(q.rid) if outs else None)
+            open_ids.add(q.rid)
+            i += 1
+        if not open_ids:
+            continue  # idle until the next arrival
+        finished = server.step()
+        now = clock() - t0
+        for rid, rejected in finished:
+            q = by_id[rid]
+            open_ids.discard(rid)
+            st.results.append(Result(rid, q.r, q.steps, q.arrival, now, now, rejected=rejected))
+    st.makespan = clock() - t0
+    s = server.stats()
+    st.iterations, st.passes = s["rounds"] - s0["rounds"], s["passes"] - s0["passes"]
+    st.max_resident_bytes, st.max_active = s["max_resident_bytes"], s["max_active"]
+    return st

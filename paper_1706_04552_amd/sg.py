@@ -56,6 +56,19 @@ def fractal(m: int, offsets) -> sg_fractal:
     return f
 
 
+class sg_server_done(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("result", ctypes.c_void_p), ("rejected", ctypes.c_int32)]
+
+
+class sg_server_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in
+                ("rounds", "passes", "completed", "rejected", "cell_steps", "max_resident_bytes",
+                 "max_active", "queued", "active", "resident_bytes")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 # Every symbol declared in include/sg.h, with its ctypes signature.
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 _vp = ctypes.c_void_p
@@ -107,6 +120,16 @@ _SIGNATURES = {
     "sg_frac_life_step": (ctypes.c_int, [ctypes.POINTER(sg_fractal), ctypes.c_int, ctypes.c_int,
                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]),
+    "sg_server_create": (ctypes.c_int, [_tunep, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.c_uint64, ctypes.c_void_p, ctypes.POINTER(_vp)]),
+    "sg_server_reserve": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.c_int]),
+    "sg_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_uint64]),
+    "sg_server_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sg_server_done), ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int)]),
+    "sg_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sg_server_stats)]),
+    "sg_server_destroy": (None, [ctypes.c_void_p]),
     "sg_tune_default": (ctypes.c_int, [_tunep]),
     "sg_batch_create": (ctypes.c_int, [ctypes.POINTER(sg_gasket), ctypes.c_int, _tunep,
                                        ctypes.POINTER(_vp)]),

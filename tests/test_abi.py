@@ -326,3 +326,24 @@ def test_rect_validation(lib):
     assert lib.sg_write_pass_rect(0, 10, 64, 4, ctypes.c_void_p(0x100008), 1, None) == sg.SG_EINVAL
     assert lib.sg_write_pass_rect(0, 10, 64, 4, None, 1, None) == sg.SG_EINVAL
     assert lib.sg_map_lambda_rect(10, 64, 4, ctypes.c_void_p(0x100004), None) == sg.SG_EINVAL
+
+
+def test_server_validation_on_the_host(lib):
+    from paper_1706_04552_amd import sg
+    h = ctypes.c_void_p()
+    good = sg.sg_tune(64, 8, 2, 256)
+    for bad in [sg.sg_tune(32, 8, 0, 256), sg.sg_tune(64, 33, 0, 256), sg.sg_tune(64, 0, 0, 256),
+                sg.sg_tune(64, 8, 65, 256), sg.sg_tune(64, 8, 0, 128)]:
+        assert lib.sg_server_create(ctypes.byref(bad), 1 << 30, 8, 0, 0, None,
+                                    ctypes.byref(h)) == sg.SG_EINVAL
+    assert lib.sg_server_create(None, 1 << 30, 8, 0, 0, None, ctypes.byref(h)) == sg.SG_EINVAL
+    assert lib.sg_server_create(ctypes.byref(good), 0, 8, 0, 0, None, ctypes.byref(h)) == sg.SG_EINVAL
+    assert lib.sg_server_create(ctypes.byref(good), 1 << 30, 0, 0, 0, None, ctypes.byref(h)) == sg.SG_EINVAL
+    assert lib.sg_server_create(ctypes.byref(good), 1 << 30, 8, 0, 0, None, None) == sg.SG_EINVAL
+    assert not h.value
+    assert lib.sg_server_reserve(None, None, 0) == sg.SG_EINVAL
+    assert lib.sg_server_submit(None, 8, 1, 0x1000, None, 0) == sg.SG_EINVAL
+    n = ctypes.c_int(-1)
+    assert lib.sg_server_step(None, None, 0, ctypes.byref(n)) == sg.SG_EINVAL
+    assert lib.sg_server_get_stats(None, None) == sg.SG_EINVAL
+    lib.sg_server_destroy(None)

@@ -12,7 +12,8 @@ import torch
 import oracle as O
 from paper_1706_04552_amd import batch as B
 from paper_1706_04552_amd import inputs, sg
-from paper_1706_04552_amd.serving import ContinuousBatcher, GpuExecutor, Request, footprint
+from paper_1706_04552_amd.serving import (ContinuousBatcher, GpuExecutor, NativeServer, Request,
+                                          footprint, serve_native)
 
 pytestmark = pytest.mark.gpu
 
@@ -163,3 +164,85 @@ def test_serving_results_equal_alone_and_respect_the_cap(horizon, budget):
         alone = solo(g, T=8).cpu().numpy()
         assert np.array_equal(res.output, alone), res.rid
         oracle_check(q.r, q.state, q.steps, res.output)
+
+
+def test_batch_benchmark_configuration_every_instance():
+    """The benchmark's batch: 512 gaskets (r ~ U{6..13}, p ~ U[0.2, 0.8]),
+    50 generations, the autotuner's launch shape, one hipGraph; every
+    instance against the oracle (whole state for r <= 8, sampled windows
+    from the dependency cone above)."""
+    steps = 50
+    specs = inputs.batch_specs(512)
+    note(f"benchmark batch: {len(specs)} gaskets, {steps} generations, autotuned")
+    hosts, gs = [], []
+    for spec in specs:
+        a0 = spec.state()
+        inp = torch.from_numpy(a0).cuda()
+        gs.append(B.Gasket(spec.r, steps, inp, torch.zeros_like(inp), torch.zeros_like(inp)))
+        hosts.append(a0)
+    tune, _ = B.autotune(gs)
+    with B.Batch(gs, tune) as bt:
+        bt.run(graph=True)
+        torch.cuda.synchronize()
+    for spec, g, a0 in zip(specs, gs, hosts):
+        got = g.out.cpu().numpy()
+        if spec.r <= 8:
+            assert np.array_equal(got, O.life_steps(spec.r, a0, steps)), spec
+        else:
+            n = 1 << spec.r
+            for (x0, y0) in [(0, 0), (n - 40, n // 2), (n // 3, n - 6)]:
+                ref = O.life_window(spec.r, a0, x0, y0, 40, 6, steps)
+                assert np.array_equal(got[y0:y0 + 6, x0:x0 + 40], ref), (spec, x0, y0)
+
+
+@pytest.mark.parametrize("horizon,budget", [(0, 0), (3 ** 10 * 64, 0), (10 ** 12, 3 ** 9 * 8)])
+def test_native_server_results_equal_alone_and_respect_the_cap(horizon, budget):
+    note(f"native server: 41 requests r=6..10 (+1 too large), horizon {horizon}, budget {budget}")
+    rng = np.random.default_rng(23)
+    reqs = []
+    for i in range(40):
+        r = int(rng.integers(6, 11))
+        steps = int(rng.integers(0, 60))
+        # half arrive together, so the first round admits several at once
+        arrival = 0.0 if i < 20 else float(rng.uniform(0, 0.02))
+        reqs.append(Request(i, arrival, r, steps, inputs.bernoulli_state(r, 0.5, 700 + i)))
+    reqs.append(Request(40, 0.005, 12, 3, inputs.bernoulli_state(12, 0.5, 740)))  # never fits
+    cap = 6 * footprint(10)
+    server = NativeServer(B.make_tune(64, 8, 2, 256), cap, 64, horizon, budget)
+    server.reserve([10, 10, 9, 9, 8, 8])
+    inits = {q.rid: torch.from_numpy(q.state).cuda() for q in reqs}
+    outs = {q.rid: torch.zeros_like(inits[q.rid]) for q in reqs}
+    st = serve_native(server, reqs, inits, outs)
+    stats = server.stats()
+    server.close()
+    assert st.max_resident_bytes <= cap and st.max_active >= 2
+    assert len(st.results) == 41 and stats["completed"] == 40 and stats["rejected"] == 1
+    assert stats["cell_steps"] == sum(3 ** q.r * q.steps for q in reqs[:40])
+    assert stats["queued"] == stats["active"] == stats["resident_bytes"] == 0
+    for res in st.results:
+        q = reqs[res.rid]
+        assert res.rejected == (q.rid == 40)
+        if res.rejected:
+            continue
+        g = B.Gasket(q.r, q.steps, inits[q.rid], torch.zeros_like(inits[q.rid]),
+                     torch.zeros_like(inits[q.rid]))
+        alone = solo(g, T=8)
+        assert torch.equal(outs[q.rid], alone), res.rid
+        oracle_check(q.r, q.state, q.steps, outs[q.rid].cpu().numpy())
+
+
+def test_native_server_reuses_its_pool_across_waves():
+    """Two waves through one server: the second reuses the buffers the first
+    released, which must again hold 0 off the gasket."""
+    note("native server: two waves of 12 requests r=7..9")
+    server = NativeServer(B.make_tune(64, 16, 0, 256), 8 * footprint(9), 16)
+    for wave in range(2):
+        reqs = [Request(i, 0.0, 7 + i % 3, 5 + 7 * i, inputs.bernoulli_state(7 + i % 3, 0.6, 800 + 50 * wave + i))
+                for i in range(12)]
+        inits = {q.rid: torch.from_numpy(q.state).cuda() for q in reqs}
+        outs = {q.rid: torch.zeros_like(inits[q.rid]) for q in reqs}
+        st = serve_native(server, reqs, inits, outs)
+        assert len(st.results) == 12 and not any(x.rejected for x in st.results)
+        for q in reqs:
+            oracle_check(q.r, q.state, q.steps, outs[q.rid].cpu().numpy())
+    server.close()
