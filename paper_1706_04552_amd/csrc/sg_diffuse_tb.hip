@@ -5,18 +5,22 @@
 //  1. load the tile plus a halo of T rows above/below and 8 cells left/right
 //     (two float4 chunks) into an LDS plane, skipping chunks with no gasket
 //     cell;
-//  2. list, once, the 4-cell chunks that hold a gasket cell (wavefront ballot
-//     + prefix count), each as one word: its region index, which of its
-//     cells are on the gasket, and every cell's count of in-grid gasket
-//     neighbours (the only per-cell data the update needs besides values);
-//  3. T times: every listed chunk applies diffuse_cell, the same function
-//     the one-step kernels use, to its 4 cells; planes ping-pong with a
-//     barrier between steps.  The 4-neighbour stencil moves information one
-//     cell per step, so cells outside the region are taken as 0 and the wrong
-//     values this makes at the region's cut edges never reach the tile in
-//     T <= 8 steps; chunks that cannot reach the tile in the steps left are
-//     skipped;
-//  4. store the tile, every 64-byte granule that holds a gasket cell in full.
+//  2. list, once, the 4-cell chunks that hold a gasket cell and can still
+//     reach the tile in T steps (wavefront ballot + prefix count), each as
+//     one word: its region index, which of its cells are on the gasket, every
+//     cell's count of in-grid gasket neighbours and its distance to the tile;
+//  3. each thread takes its listed chunks into registers: the chunk's LDS
+//     offset, the number of steps in which it can still reach the tile, and
+//     per cell -deg and a weight (alpha on the gasket, 0 off it);
+//  4. T times: every held chunk updates its 4 cells with the arithmetic of
+//     diffuse_cell, the function the one-step kernels use, as
+//     fma(w, fma(-deg, u, (W + E) + (N + S)), u); off the gasket w = 0 keeps
+//     the value, which is 0.  Planes ping-pong with a barrier between steps.
+//     The 4-neighbour stencil moves information one cell per step, so cells
+//     outside the region are taken as 0 and the wrong values this makes at
+//     the region's cut edges never reach the tile in T <= 8 steps; a chunk
+//     stops once it can no longer reach the tile in the steps left;
+//  5. store the tile, every 64-byte granule that holds a gasket cell in full.
 //
 // Plane rows have a pitch of the region width + 4 floats: the 4 floats before
 // a row's first chunk are 0, so the west neighbour of the first chunk and the
@@ -36,6 +40,9 @@ struct DtGeom {
   static constexpr int CC = CW / 4;              // region chunks per row
   static constexpr int PW = CW + 4;              // plane pitch (one zero chunk per row)
   static constexpr int NT = RHO >= 64 ? 512 : 256;
+  // chunks of the largest region, and how many one thread may hold
+  static constexpr int SLOTS = (RHO + 2 * kMaxDiffuseStepsPerPass) * CC;
+  static constexpr int KMAX = (SLOTS + NT - 1) / NT;
 };
 
 template <int RHO>
@@ -46,8 +53,32 @@ size_t dt_lds_bytes(int T) {
 }
 
 // Chunk word: region chunk index (11 bits) | gasket cells (4 bits) << 11 |
-// neighbour count of cell j (3 bits) << (15 + 3j).
+// neighbour count of cell j (3 bits) << (15 + 3j) | distance to the tile
+// (cells, < T) << 27.
 constexpr int kChunkBits = 11;
+constexpr int kDistShift = 27;
+
+// Distance (in steps of the 4-neighbour stencil) from region chunk (i, c) to
+// the tile, whose rows are T .. T + RHO - 1 and columns kDtHalo .. kDtHalo +
+// RHO - 1 of the region.
+// Gasket cells of the 4-cell chunk at column x (a multiple of 4) of row y, as
+// a 4-bit mask (bit j: cell x + j): cell x + j is on the gasket iff x & y == 0
+// and j & (y mod 4) == 0.  Rows outside the grid hold no cell.
+__device__ __forceinline__ uint32_t chunk_row_mask(int x, int y, int n) {
+  return (y >= 0 && y < n && (x & y) == 0) ? (0x135Fu >> (4 * (y & 3))) & 0xfu : 0u;
+}
+
+// Bit j of a 4-bit mask moved to bit 3j (the low bit of cell j's count field).
+__device__ __forceinline__ uint32_t spread_nibble(uint32_t m) {
+  return (m & 1u) | ((m & 2u) << 2) | ((m & 4u) << 4) | ((m & 8u) << 6);
+}
+
+template <int RHO>
+__device__ __forceinline__ int chunk_distance(int i, int c, int T) {
+  const int dy = max(0, max(T - i, i - (T + RHO - 1)));
+  const int dx = max(0, max(kDtHalo - 4 * c - 3, 4 * c - kDtHalo - RHO + 1));
+  return max(dx, dy);
+}
 
 template <int RHO, bool LAMBDA>
 __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__restrict__ in,
@@ -81,42 +112,59 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
   float *plane1 = flds + R * G::PW + 4;
   uint32_t *chunks = reinterpret_cast<uint32_t *>(plane1 + R * G::PW + 4);  // R * CC
 
-  for (int k = tid; k < 2 * (R * G::PW + 4); k += NT) flds[k] = 0.0f;
+  // 1. load: every load of the thread is issued before its first wait
+  constexpr int KS = G::KMAX;  // region chunks per thread, at most
+  const int nslots = R * G::CC;
+  float4 v[KS];
+  bool has[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    const int e = tid + kk * NT;
+    const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
+    const int y = yr0 + i, x = xr0 + 4 * c;
+    has[kk] = e < nslots && y >= 0 && y < n && x >= 0 && x < n && (x & y) == 0;
+    v[kk] = has[kk] ? *reinterpret_cast<const float4 *>(in + (size_t)y * n + x)
+                    : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
   if (tid == 0) nchunk = 0u;
   __syncthreads();
 
-  // 1. load
-  for (int e = tid; e < R * G::CC; e += NT) {
-    const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
-    const int y = yr0 + i, x = xr0 + 4 * c;
-    if (y < 0 || y >= n || x < 0 || x >= n || (x & y) != 0) continue;
-    const float4 v = *reinterpret_cast<const float4 *>(in + (size_t)y * n + x);
-    *reinterpret_cast<float4 *>(plane0 + i * G::PW + 4 + 4 * c) = v;
+  // every float of both planes is written once: the zero chunk before each
+  // row (and after the last), and each region chunk (its value, or 0)
+  float4 *q0 = reinterpret_cast<float4 *>(plane0);
+  float4 *q1 = reinterpret_cast<float4 *>(plane1);
+  constexpr int PQ = G::PW / 4;  // plane pitch in chunks
+  const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int k = tid; k <= R; k += NT) {
+    q0[k * PQ] = zero4;
+    q1[k * PQ] = zero4;
   }
 
-  // 2. the chunks that hold a gasket cell, with their cells' data
+  // 2. the chunks that hold a gasket cell and can reach the tile, with their
+  // cells' data: 4-bit masks of the gasket cells of this row and the rows
+  // above and below give each cell's neighbour count, summed in 3-bit fields
   const int lane = __lane_id();
-  for (int base = 0; base < R * G::CC; base += NT) {
-    const int e = base + tid;
-    uint32_t word = 0u;
-    bool live = false;
-    if (e < R * G::CC) {
-      const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
-      const int y = yr0 + i, x = xr0 + 4 * c;
-      live = y >= 0 && y < n && x >= 0 && x < n && (x & y) == 0;
-      if (live) {
-        word = (uint32_t)e;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int xj = x + j;
-          const bool self = (xj & y) == 0;
-          const int deg = (int)(xj > 0 && ((xj - 1) & y) == 0) +
-                          (int)(xj + 1 < n && ((xj + 1) & y) == 0) +
-                          (int)(y > 0 && (xj & (y - 1)) == 0) +
-                          (int)(y + 1 < n && (xj & (y + 1)) == 0);
-          word |= ((uint32_t)self << (kChunkBits + j)) | ((uint32_t)deg << (15 + 3 * j));
-        }
-      }
+  for (int kk = 0; kk < KS; ++kk) {
+    const int e = tid + kk * NT;
+    const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
+    if (e < nslots) {
+      q0[i * PQ + 1 + c] = v[kk];
+      q1[i * PQ + 1 + c] = zero4;
+    }
+    const int y = yr0 + i, x = xr0 + 4 * c;
+    const int d = chunk_distance<RHO>(i, c, T);
+    const bool live = has[kk] && d < T;
+    uint32_t word = 0u;
+    if (live) {
+      const uint32_t S = chunk_row_mask(x, y, n), U = chunk_row_mask(x, y - 1, n),
+                     D = chunk_row_mask(x, y + 1, n);
+      const uint32_t lb = (x > 0 && ((x - 1) & y) == 0) ? 1u : 0u;
+      const uint32_t rb = (x + 4 < n && ((x + 4) & y) == 0) ? 1u : 0u;
+      const uint32_t L = ((S << 1) | lb) & 0xfu, Rm = (S >> 1) | (rb << 3);
+      const uint32_t degs = spread_nibble(U) + spread_nibble(D) + spread_nibble(L) +
+                            spread_nibble(Rm);
+      word = (uint32_t)e | (S << kChunkBits) | (degs << 15) | ((uint32_t)d << kDistShift);
     }
     const uint64_t ball = __ballot(live);
     const uint32_t before = (uint32_t)__popcll(ball & ((1ull << lane) - 1ull));
@@ -128,19 +176,41 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
   __syncthreads();
   const int nc = (int)nchunk;
 
-  // 3. T steps
-  for (int s = 0; s < T; ++s) {
-    const float *src = (s & 1) ? plane1 : plane0;
-    float *dst = (s & 1) ? plane0 : plane1;
-    const int reach = T - s - 1;  // steps left after this one
-    for (int k = tid; k < nc; k += NT) {
+  // 3. this thread's chunks, in registers
+  constexpr int KMAX = G::KMAX;
+  int off[KMAX], steps_live[KMAX];
+  float nd[KMAX][4], wt[KMAX][4];
+#pragma unroll
+  for (int kk = 0; kk < KMAX; ++kk) {
+    const int k = tid + kk * NT;
+    off[kk] = 0;
+    steps_live[kk] = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) nd[kk][j] = wt[kk][j] = 0.0f;
+    if (k < nc) {
       const uint32_t word = chunks[k];
       const int e = (int)(word & ((1u << kChunkBits) - 1u));
       const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
-      // skip chunks that cannot reach the tile in the steps left
-      if (i < T - reach || i >= T + RHO + reach) continue;
-      if (4 * c + 4 <= kDtHalo - reach || 4 * c >= kDtHalo + RHO + reach) continue;
-      const float *p = src + i * G::PW + 4 + 4 * c;
+      off[kk] = i * G::PW + 4 + 4 * c;
+      steps_live[kk] = T - (int)(word >> kDistShift);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bool self = (word >> (kChunkBits + j)) & 1u;
+        const float deg = (float)((word >> (15 + 3 * j)) & 7u);
+        nd[kk][j] = self ? -deg : 0.0f;
+        wt[kk][j] = self ? alpha : 0.0f;
+      }
+    }
+  }
+
+  // 4. T steps
+  for (int s = 0; s < T; ++s) {
+    const float *src = (s & 1) ? plane1 : plane0;
+    float *dst = (s & 1) ? plane0 : plane1;
+#pragma unroll
+    for (int kk = 0; kk < KMAX; ++kk) {
+      if (s >= steps_live[kk]) continue;  // cannot reach the tile any more
+      const float *p = src + off[kk];
       const float4 C = *reinterpret_cast<const float4 *>(p);
       const float4 N = *reinterpret_cast<const float4 *>(p - G::PW);
       const float4 S = *reinterpret_cast<const float4 *>(p + G::PW);
@@ -152,18 +222,16 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
       for (int j = 0; j < 4; ++j) {
         const float w = j == 0 ? Wn : cu[j - 1];
         const float ee = j == 3 ? En : cu[j + 1];
-        const float deg = (float)((word >> (15 + 3 * j)) & 7u);
-        const bool self = (word >> (kChunkBits + j)) & 1u;
-        o[j] = diffuse_cell(cu[j], w, ee, nu[j], su[j], deg, self, alpha);
+        o[j] = __builtin_fmaf(wt[kk][j], __builtin_fmaf(nd[kk][j], cu[j], (w + ee) + (nu[j] + su[j])),
+                              cu[j]);
       }
-      *reinterpret_cast<float4 *>(dst + i * G::PW + 4 + 4 * c) =
-          make_float4(o[0], o[1], o[2], o[3]);
+      *reinterpret_cast<float4 *>(dst + off[kk]) = make_float4(o[0], o[1], o[2], o[3]);
     }
     __syncthreads();
   }
   const float *fin = (T & 1) ? plane1 : plane0;
 
-  // 4. store the tile, whole 64-byte granules (16 floats)
+  // 5. store the tile, whole 64-byte granules (16 floats)
   constexpr int TC = RHO / 4;
   for (int e = tid; e < RHO * TC; e += NT) {
     const int ty = e / TC, c = e - (e / TC) * TC;
