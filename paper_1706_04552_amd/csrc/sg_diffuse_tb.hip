@@ -3,28 +3,34 @@
 // One workgroup owns one rho x rho tile (rho in {32, 64}) of the map and
 // advances it by T <= 8 explicit diffusion steps per pass:
 //  1. load the tile plus a halo of T rows above/below and 8 cells left/right
-//     (two float4 chunks) into an LDS plane, skipping chunks with no gasket
-//     cell;
-//  2. list, once, the 4-cell chunks that hold a gasket cell and can still
-//     reach the tile in T steps (wavefront ballot + prefix count), each as
-//     one word: its region index, which of its cells are on the gasket, every
-//     cell's count of in-grid gasket neighbours and its distance to the tile;
+//     (two float4 chunks) into registers, every load issued before the first
+//     wait, skipping chunks with no gasket cell;
+//  2. write the first plane, and list the 4-cell chunks that hold a gasket
+//     cell and can reach the tile in T steps (wavefront ballot + prefix
+//     count), each as one word: its
+//     region index, which of its cells are on the gasket, every cell's count
+//     of in-grid gasket neighbours and its distance to the tile.  The list is
+//     built in the second plane's memory, which is not in use yet;
 //  3. each thread takes its listed chunks into registers: the chunk's LDS
 //     offset, the number of steps in which it can still reach the tile, and
 //     per cell -deg and a weight (alpha on the gasket, 0 off it);
-//  4. T times: every held chunk updates its 4 cells with the arithmetic of
-//     diffuse_cell, the function the one-step kernels use, as
+//  4. clear the second plane, then T times: every
+//     held chunk updates its 4 cells with the arithmetic of diffuse_cell, the
+//     function the one-step kernels use, as
 //     fma(w, fma(-deg, u, (W + E) + (N + S)), u); off the gasket w = 0 keeps
-//     the value, which is 0.  Planes ping-pong with a barrier between steps.
-//     The 4-neighbour stencil moves information one cell per step, so cells
-//     outside the region are taken as 0 and the wrong values this makes at
-//     the region's cut edges never reach the tile in T <= 8 steps; a chunk
-//     stops once it can no longer reach the tile in the steps left;
+//     the value, which is 0.  A chunk's own values stay in registers; the
+//     neighbours come from the other plane, and the planes ping-pong with a
+//     barrier between steps;
 //  5. store the tile, every 64-byte granule that holds a gasket cell in full.
 //
-// Plane rows have a pitch of the region width + 4 floats: the 4 floats before
-// a row's first chunk are 0, so the west neighbour of the first chunk and the
-// east neighbour of the last chunk (the next row's first float) read 0.
+// The 4-neighbour stencil moves information one cell per step.  Cells outside
+// the region hold wrong values (the plane has no cells there: a row's west
+// neighbour of its first chunk is the previous row's last cell, and so on),
+// and a chunk stops updating once it can no longer reach the tile in the
+// steps left, which leaves stale values behind it.  Every such cell is more
+// steps away from the tile than remain, so the tile's values are exactly
+// those of T one-step passes.  Rows 0 and R - 1 of the region are T cells from
+// the tile, so no updated chunk reads outside the plane.
 #include "sg_device.h"
 #include "sg_launch.h"
 
@@ -36,9 +42,8 @@ constexpr int kDtHalo = 8;  // halo columns each side: two float4 chunks
 
 template <int RHO>
 struct DtGeom {
-  static constexpr int CW = RHO + 2 * kDtHalo;  // region columns (floats)
+  static constexpr int CW = RHO + 2 * kDtHalo;  // region columns = plane pitch (floats)
   static constexpr int CC = CW / 4;              // region chunks per row
-  static constexpr int PW = CW + 4;              // plane pitch (one zero chunk per row)
   static constexpr int NT = RHO >= 64 ? 512 : 256;
   // chunks of the largest region, and how many one thread may hold
   static constexpr int SLOTS = (RHO + 2 * kMaxDiffuseStepsPerPass) * CC;
@@ -48,19 +53,15 @@ struct DtGeom {
 template <int RHO>
 size_t dt_lds_bytes(int T) {
   using G = DtGeom<RHO>;
-  const int R = RHO + 2 * T;
-  return sizeof(float) * (size_t)(2 * (R * G::PW + 4)) + sizeof(uint32_t) * (size_t)(R * G::CC);
+  return sizeof(float) * 2 * (size_t)(RHO + 2 * T) * G::CW;
 }
 
 // Chunk word: region chunk index (11 bits) | gasket cells (4 bits) << 11 |
 // neighbour count of cell j (3 bits) << (15 + 3j) | distance to the tile
-// (cells, < T) << 27.
+// (< T) << 27.
 constexpr int kChunkBits = 11;
 constexpr int kDistShift = 27;
 
-// Distance (in steps of the 4-neighbour stencil) from region chunk (i, c) to
-// the tile, whose rows are T .. T + RHO - 1 and columns kDtHalo .. kDtHalo +
-// RHO - 1 of the region.
 // Gasket cells of the 4-cell chunk at column x (a multiple of 4) of row y, as
 // a 4-bit mask (bit j: cell x + j): cell x + j is on the gasket iff x & y == 0
 // and j & (y mod 4) == 0.  Rows outside the grid hold no cell.
@@ -73,6 +74,9 @@ __device__ __forceinline__ uint32_t spread_nibble(uint32_t m) {
   return (m & 1u) | ((m & 2u) << 2) | ((m & 4u) << 4) | ((m & 8u) << 6);
 }
 
+// Distance (in steps of the 4-neighbour stencil) from region chunk (i, c) to
+// the tile, whose rows are T .. T + RHO - 1 and columns kDtHalo .. kDtHalo +
+// RHO - 1 of the region.
 template <int RHO>
 __device__ __forceinline__ int chunk_distance(int i, int c, int T) {
   const int dy = max(0, max(T - i, i - (T + RHO - 1)));
@@ -88,7 +92,8 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
                                                                 float alpha) {
   using G = DtGeom<RHO>;
   constexpr int NT = G::NT;
-  static_assert((RHO + 2 * 8) * G::CC < (1 << kChunkBits), "chunk index fits its field");
+  constexpr int KS = G::KMAX;
+  static_assert(G::SLOTS < (1 << kChunkBits), "chunk index fits its field");
   extern __shared__ __align__(16) float flds[];
   __shared__ uint32_t nchunk;
   const uint64_t t = tile_base + logical_group();
@@ -102,19 +107,17 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
     if ((bx & by) != 0u) return;
   }
   const int tid = threadIdx.x;
+  const int lane = __lane_id();
   const int n = 1 << r;
   const int X0 = (int)bx * RHO, Y0 = (int)by * RHO;
   const int xr0 = X0 - kDtHalo, yr0 = Y0 - T;  // region origin
   const int R = RHO + 2 * T;
-  // region cell (i, c) of a plane is at i * PW + 4 + c; 4 trailing zero
-  // floats after the last row serve its last chunk's east neighbour
-  float *plane0 = flds;
-  float *plane1 = flds + R * G::PW + 4;
-  uint32_t *chunks = reinterpret_cast<uint32_t *>(plane1 + R * G::PW + 4);  // R * CC
-
-  // 1. load: every load of the thread is issued before its first wait
-  constexpr int KS = G::KMAX;  // region chunks per thread, at most
   const int nslots = R * G::CC;
+  // region cell (i, x) of a plane is at i * CW + x
+  float *plane0 = flds;
+  float *plane1 = flds + R * G::CW;
+
+  // 1. load
   float4 v[KS];
   bool has[KS];
 #pragma unroll
@@ -126,32 +129,26 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
     v[kk] = has[kk] ? *reinterpret_cast<const float4 *>(in + (size_t)y * n + x)
                     : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
+  // plane0 takes the loaded values (chunk e starts at float 4e, since rows are
+  // CW = 4 CC floats)
+  float4 *q0 = reinterpret_cast<float4 *>(plane0);
+  float4 *q1 = reinterpret_cast<float4 *>(plane1);
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) {
+    const int e = tid + kk * NT;
+    if (e < nslots) q0[e] = v[kk];
+  }
   if (tid == 0) nchunk = 0u;
   __syncthreads();
 
-  // every float of both planes is written once: the zero chunk before each
-  // row (and after the last), and each region chunk (its value, or 0)
-  float4 *q0 = reinterpret_cast<float4 *>(plane0);
-  float4 *q1 = reinterpret_cast<float4 *>(plane1);
-  constexpr int PQ = G::PW / 4;  // plane pitch in chunks
-  const float4 zero4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  for (int k = tid; k <= R; k += NT) {
-    q0[k * PQ] = zero4;
-    q1[k * PQ] = zero4;
-  }
-
-  // 2. the chunks that hold a gasket cell and can reach the tile, with their
-  // cells' data: 4-bit masks of the gasket cells of this row and the rows
-  // above and below give each cell's neighbour count, summed in 3-bit fields
-  const int lane = __lane_id();
+  // 2. the list, built in plane1's memory: 4-bit masks of the gasket cells of
+  // the chunk's row and the rows above and below give each cell's neighbour
+  // count, summed in 3-bit fields
+  uint32_t *list = reinterpret_cast<uint32_t *>(plane1);
 #pragma unroll
   for (int kk = 0; kk < KS; ++kk) {
     const int e = tid + kk * NT;
     const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
-    if (e < nslots) {
-      q0[i * PQ + 1 + c] = v[kk];
-      q1[i * PQ + 1 + c] = zero4;
-    }
     const int y = yr0 + i, x = xr0 + 4 * c;
     const int d = chunk_distance<RHO>(i, c, T);
     const bool live = has[kk] && d < T;
@@ -160,38 +157,36 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
       const uint32_t S = chunk_row_mask(x, y, n), U = chunk_row_mask(x, y - 1, n),
                      D = chunk_row_mask(x, y + 1, n);
       const uint32_t lb = (x > 0 && ((x - 1) & y) == 0) ? 1u : 0u;
-      const uint32_t rb = (x + 4 < n && ((x + 4) & y) == 0) ? 1u : 0u;
-      const uint32_t L = ((S << 1) | lb) & 0xfu, Rm = (S >> 1) | (rb << 3);
+      const uint32_t rbit = (x + 4 < n && ((x + 4) & y) == 0) ? 1u : 0u;
+      const uint32_t L = ((S << 1) | lb) & 0xfu, Rm = (S >> 1) | (rbit << 3);
       const uint32_t degs = spread_nibble(U) + spread_nibble(D) + spread_nibble(L) +
                             spread_nibble(Rm);
       word = (uint32_t)e | (S << kChunkBits) | (degs << 15) | ((uint32_t)d << kDistShift);
     }
     const uint64_t ball = __ballot(live);
     const uint32_t before = (uint32_t)__popcll(ball & ((1ull << lane) - 1ull));
-    uint32_t off = 0u;
-    if (lane == 0 && ball != 0ull) off = atomicAdd(&nchunk, (uint32_t)__popcll(ball));
-    off = __shfl(off, 0);
-    if (live) chunks[off + before] = word;
+    uint32_t base = 0u;
+    if (lane == 0 && ball != 0ull) base = atomicAdd(&nchunk, (uint32_t)__popcll(ball));
+    base = __shfl(base, 0);
+    if (live) list[base + before] = word;
   }
   __syncthreads();
   const int nc = (int)nchunk;
 
   // 3. this thread's chunks, in registers
-  constexpr int KMAX = G::KMAX;
-  int off[KMAX], steps_live[KMAX];
-  float nd[KMAX][4], wt[KMAX][4];
+  int off[KS], steps_live[KS];
+  float nd[KS][4], wt[KS][4];
 #pragma unroll
-  for (int kk = 0; kk < KMAX; ++kk) {
+  for (int kk = 0; kk < KS; ++kk) {
     const int k = tid + kk * NT;
     off[kk] = 0;
     steps_live[kk] = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) nd[kk][j] = wt[kk][j] = 0.0f;
     if (k < nc) {
-      const uint32_t word = chunks[k];
+      const uint32_t word = list[k];
       const int e = (int)(word & ((1u << kChunkBits) - 1u));
-      const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
-      off[kk] = i * G::PW + 4 + 4 * c;
+      off[kk] = 4 * e;  // rows are CW = 4 CC floats, so chunk e starts at float 4e
       steps_live[kk] = T - (int)(word >> kDistShift);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -202,30 +197,38 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
       }
     }
   }
+  __syncthreads();  // the list is read before plane1 is cleared
 
-  // 4. T steps
+  // 4. plane1 cleared, then T steps
+  for (int e = tid; e < nslots; e += NT) q1[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  __syncthreads();
+  float4 cur[KS];
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk)
+    cur[kk] = steps_live[kk] > 0 ? *reinterpret_cast<const float4 *>(plane0 + off[kk])
+                                 : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   for (int s = 0; s < T; ++s) {
     const float *src = (s & 1) ? plane1 : plane0;
     float *dst = (s & 1) ? plane0 : plane1;
 #pragma unroll
-    for (int kk = 0; kk < KMAX; ++kk) {
+    for (int kk = 0; kk < KS; ++kk) {
       if (s >= steps_live[kk]) continue;  // cannot reach the tile any more
       const float *p = src + off[kk];
-      const float4 C = *reinterpret_cast<const float4 *>(p);
-      const float4 N = *reinterpret_cast<const float4 *>(p - G::PW);
-      const float4 S = *reinterpret_cast<const float4 *>(p + G::PW);
+      const float4 N = *reinterpret_cast<const float4 *>(p - G::CW);
+      const float4 S = *reinterpret_cast<const float4 *>(p + G::CW);
       const float Wn = p[-1], En = p[4];
-      const float cu[4] = {C.x, C.y, C.z, C.w}, nu[4] = {N.x, N.y, N.z, N.w};
-      const float su[4] = {S.x, S.y, S.z, S.w};
+      const float cu[4] = {cur[kk].x, cur[kk].y, cur[kk].z, cur[kk].w};
+      const float nu[4] = {N.x, N.y, N.z, N.w}, su[4] = {S.x, S.y, S.z, S.w};
       float o[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const float w = j == 0 ? Wn : cu[j - 1];
         const float ee = j == 3 ? En : cu[j + 1];
-        o[j] = __builtin_fmaf(wt[kk][j], __builtin_fmaf(nd[kk][j], cu[j], (w + ee) + (nu[j] + su[j])),
-                              cu[j]);
+        o[j] = __builtin_fmaf(wt[kk][j],
+                              __builtin_fmaf(nd[kk][j], cu[j], (w + ee) + (nu[j] + su[j])), cu[j]);
       }
-      *reinterpret_cast<float4 *>(dst + off[kk]) = make_float4(o[0], o[1], o[2], o[3]);
+      cur[kk] = make_float4(o[0], o[1], o[2], o[3]);
+      *reinterpret_cast<float4 *>(dst + off[kk]) = cur[kk];
     }
     __syncthreads();
   }
@@ -237,9 +240,8 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
     const int ty = e / TC, c = e - (e / TC) * TC;
     const int y = Y0 + ty, x = X0 + 4 * c;
     if (((x & ~15) & y) != 0) continue;
-    const float4 v =
-        *reinterpret_cast<const float4 *>(fin + (T + ty) * G::PW + 4 + kDtHalo + 4 * c);
-    *reinterpret_cast<float4 *>(out + (size_t)y * n + x) = v;
+    const float4 w = *reinterpret_cast<const float4 *>(fin + (T + ty) * G::CW + kDtHalo + 4 * c);
+    *reinterpret_cast<float4 *>(out + (size_t)y * n + x) = w;
   }
 }
 
