@@ -7,13 +7,13 @@
 //     wait, skipping chunks with no gasket cell;
 //  2. write the first plane, and list the 4-cell chunks that hold a gasket
 //     cell and can reach the tile in T steps (wavefront ballot + prefix
-//     count), each as one word: its
-//     region index, which of its cells are on the gasket, every cell's count
-//     of in-grid gasket neighbours and its distance to the tile.  The list is
-//     built in the second plane's memory, which is not in use yet;
+//     count), each as one word: its region index and its distance to the
+//     tile.  The list is built in the second plane's memory, which is not in
+//     use yet;
 //  3. each thread takes its listed chunks into registers: the chunk's LDS
 //     offset, the number of steps in which it can still reach the tile, and
-//     per cell -deg and a weight (alpha on the gasket, 0 off it);
+//     per cell -deg (its count of in-grid gasket neighbours) and a weight
+//     (alpha on the gasket, 0 off it);
 //  4. clear the second plane, then T times: every
 //     held chunk updates its 4 cells with the arithmetic of diffuse_cell, the
 //     function the one-step kernels use, as
@@ -56,9 +56,7 @@ size_t dt_lds_bytes(int T) {
   return sizeof(float) * 2 * (size_t)(RHO + 2 * T) * G::CW;
 }
 
-// Chunk word: region chunk index (11 bits) | gasket cells (4 bits) << 11 |
-// neighbour count of cell j (3 bits) << (15 + 3j) | distance to the tile
-// (< T) << 27.
+// List word: region chunk index (11 bits) | distance to the tile (< T) << 27.
 constexpr int kChunkBits = 11;
 constexpr int kDistShift = 27;
 
@@ -141,28 +139,15 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
   if (tid == 0) nchunk = 0u;
   __syncthreads();
 
-  // 2. the list, built in plane1's memory: 4-bit masks of the gasket cells of
-  // the chunk's row and the rows above and below give each cell's neighbour
-  // count, summed in 3-bit fields
+  // 2. the list, built in plane1's memory
   uint32_t *list = reinterpret_cast<uint32_t *>(plane1);
 #pragma unroll
   for (int kk = 0; kk < KS; ++kk) {
     const int e = tid + kk * NT;
     const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
-    const int y = yr0 + i, x = xr0 + 4 * c;
     const int d = chunk_distance<RHO>(i, c, T);
     const bool live = has[kk] && d < T;
-    uint32_t word = 0u;
-    if (live) {
-      const uint32_t S = chunk_row_mask(x, y, n), U = chunk_row_mask(x, y - 1, n),
-                     D = chunk_row_mask(x, y + 1, n);
-      const uint32_t lb = (x > 0 && ((x - 1) & y) == 0) ? 1u : 0u;
-      const uint32_t rbit = (x + 4 < n && ((x + 4) & y) == 0) ? 1u : 0u;
-      const uint32_t L = ((S << 1) | lb) & 0xfu, Rm = (S >> 1) | (rbit << 3);
-      const uint32_t degs = spread_nibble(U) + spread_nibble(D) + spread_nibble(L) +
-                            spread_nibble(Rm);
-      word = (uint32_t)e | (S << kChunkBits) | (degs << 15) | ((uint32_t)d << kDistShift);
-    }
+    const uint32_t word = (uint32_t)e | ((uint32_t)d << kDistShift);
     const uint64_t ball = __ballot(live);
     const uint32_t before = (uint32_t)__popcll(ball & ((1ull << lane) - 1ull));
     uint32_t base = 0u;
@@ -172,6 +157,7 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
   }
   __syncthreads();
   const int nc = (int)nchunk;
+  const int kheld = (nc + NT - 1) / NT;  // register slots in use (uniform)
 
   // 3. this thread's chunks, in registers
   int off[KS], steps_live[KS];
@@ -183,15 +169,26 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
     steps_live[kk] = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) nd[kk][j] = wt[kk][j] = 0.0f;
-    if (k < nc) {
+    if (kk < kheld && k < nc) {
       const uint32_t word = list[k];
       const int e = (int)(word & ((1u << kChunkBits) - 1u));
       off[kk] = 4 * e;  // rows are CW = 4 CC floats, so chunk e starts at float 4e
       steps_live[kk] = T - (int)(word >> kDistShift);
+      // 4-bit masks of the gasket cells of the chunk's row and the rows above
+      // and below give each cell's neighbour count, summed in 3-bit fields
+      const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
+      const int y = yr0 + i, x = xr0 + 4 * c;
+      const uint32_t S = chunk_row_mask(x, y, n), U = chunk_row_mask(x, y - 1, n),
+                     D = chunk_row_mask(x, y + 1, n);
+      const uint32_t lb = (x > 0 && ((x - 1) & y) == 0) ? 1u : 0u;
+      const uint32_t rbit = (x + 4 < n && ((x + 4) & y) == 0) ? 1u : 0u;
+      const uint32_t L = ((S << 1) | lb) & 0xfu, Rm = (S >> 1) | (rbit << 3);
+      const uint32_t degs =
+          spread_nibble(U) + spread_nibble(D) + spread_nibble(L) + spread_nibble(Rm);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool self = (word >> (kChunkBits + j)) & 1u;
-        const float deg = (float)((word >> (15 + 3 * j)) & 7u);
+        const bool self = (S >> j) & 1u;
+        const float deg = (float)((degs >> (3 * j)) & 7u);
         nd[kk][j] = self ? -deg : 0.0f;
         wt[kk][j] = self ? alpha : 0.0f;
       }
@@ -205,13 +202,14 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
   float4 cur[KS];
 #pragma unroll
   for (int kk = 0; kk < KS; ++kk)
-    cur[kk] = steps_live[kk] > 0 ? *reinterpret_cast<const float4 *>(plane0 + off[kk])
+    cur[kk] = kk < kheld && steps_live[kk] > 0 ? *reinterpret_cast<const float4 *>(plane0 + off[kk])
                                  : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   for (int s = 0; s < T; ++s) {
     const float *src = (s & 1) ? plane1 : plane0;
     float *dst = (s & 1) ? plane0 : plane1;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
+      if (kk >= kheld) break;             // no thread holds a chunk here
       if (s >= steps_live[kk]) continue;  // cannot reach the tile any more
       const float *p = src + off[kk];
       const float4 N = *reinterpret_cast<const float4 *>(p - G::CW);
