@@ -360,6 +360,9 @@ def bench_serving(torch, sg, inputs, qps_list, count, cap_gb, horizon_cells=None
             "budget_cells": budget_cells, "by_qps": results}
 
 
+EXTRA_LEGS = ("sweep", "diffusion", "batched", "fractals", "serving")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -372,7 +375,9 @@ def main():
                     help="skip the one-launch-per-generation sweep")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the diffusion, batched and serving legs")
+                    help="skip the sweep, diffusion, batched, fractal and serving legs")
+    ap.add_argument("--extras", nargs="*", choices=EXTRA_LEGS, default=list(EXTRA_LEGS),
+                    help="which of the extra legs to run (default: all)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--serve-qps", type=float, nargs="*", default=[1000.0, 4000.0, 16000.0])
     ap.add_argument("--serve-requests", type=int, default=400)
@@ -513,18 +518,24 @@ def main():
                 "launch_duration_us": round(launch_us, 2), "launches": launches}
 
     extras = {}
-    if not args.no_extras:
+    legs = [] if args.no_extras else args.extras
+    if legs:
         del A, B
         torch.cuda.empty_cache()
+    if "sweep" in legs:
         extras["sweep_one_launch_per_step"] = bench_sweep(torch, sg, inputs, (10, 12, 14),
                                                           (4, 8, 16, 32, 64, 128, 256), 100)
-        extras["diffusion"] = bench_diffusion(torch, sg, inputs, (16, 64, 128, 256), args.steps, args.warmup)
+    if "diffusion" in legs:
+        extras["diffusion"] = bench_diffusion(torch, sg, inputs, (16, 64, 128, 256), args.steps,
+                                              args.warmup)
+    if "batched" in legs:
         extras["batched"] = bench_batched(torch, sg, inputs, args.batch_count, 50, 5)
+    if "fractals" in legs:
         extras["other_fractals"] = bench_fractals(torch, sg, 10, 20)
         torch.cuda.empty_cache()
-        torch.cuda.empty_cache()
-        extras["serving"] = bench_serving(torch, sg, inputs, args.serve_qps, args.serve_requests, 200.0,
-                                          int(args.serve_horizon) or None,
+    if "serving" in legs:
+        extras["serving"] = bench_serving(torch, sg, inputs, args.serve_qps, args.serve_requests,
+                                          200.0, int(args.serve_horizon) or None,
                                           int(args.serve_budget) or None)
         torch.cuda.empty_cache()
 
