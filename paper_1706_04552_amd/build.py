@@ -44,7 +44,9 @@ def source_digest(names=None) -> str:
     describes the current kernels."""
     import hashlib
     h = hashlib.sha256()
-    h.update(" ".join(HIP_FLAGS).encode())
+    # the flags with the checkout's own path left out, so that a copy of the
+    # tree elsewhere gives the same digest
+    h.update(" ".join(f.replace(ROOT, ".") for f in HIP_FLAGS).encode())
     if names is None:
         files = sorted(glob.glob(os.path.join(CSRC, "*")) + [os.path.join(ROOT, "include", "sg.h")])
     else:

@@ -347,3 +347,20 @@ def test_server_validation_on_the_host(lib):
     assert lib.sg_server_step(None, None, 0, ctypes.byref(n)) == sg.SG_EINVAL
     assert lib.sg_server_get_stats(None, None) == sg.SG_EINVAL
     lib.sg_server_destroy(None)
+
+
+def test_source_digest_does_not_depend_on_the_checkout_path(tmp_path):
+    # a stored profile names the digest of the kernel sources it measured; a
+    # copy of the tree elsewhere (another machine's checkout) must agree
+    import shutil
+    from paper_1706_04552_amd import build
+    pkg = tmp_path / "paper_1706_04552_amd"
+    shutil.copytree(os.path.join(build.ROOT, "paper_1706_04552_amd", "csrc"), pkg / "csrc")
+    shutil.copy(os.path.join(build.ROOT, "paper_1706_04552_amd", "build.py"), pkg / "build.py")
+    (pkg / "__init__.py").write_text("")
+    shutil.copytree(os.path.join(build.ROOT, "include"), tmp_path / "include")
+    code = ("from paper_1706_04552_amd import build as b; "
+            "print(b.source_digest(b.LIFE_TB_SOURCES), b.source_digest())")
+    out = subprocess.run([sys.executable, "-c", code], cwd=tmp_path, capture_output=True,
+                         text=True, check=True).stdout.split()
+    assert out == [build.source_digest(build.LIFE_TB_SOURCES), build.source_digest()]
