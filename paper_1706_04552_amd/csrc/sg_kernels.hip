@@ -294,16 +294,18 @@ __global__ __launch_bounds__(NT) void k_diffuse(const float *__restrict__ in,
 
 constexpr int kBand = 16;  // rows per lane band in the strip layout
 
-// HBM stores below a 64-byte granule cost a read-modify-write, and sparse
-// reads run fastest as whole 128-byte lines.  When a tile row spans whole
-// granules (rho >= 64 bytes), the strip kernels store every 64-byte granule
-// that holds a gasket cell in full (0 on its off-gasket cells) and load every
-// 128-byte line (or the whole row, if shorter) that holds one.  A granule that
-// holds a gasket cell is exactly one whose first cell does: x0 & y == 0 for a
-// granule starting at x0 (a multiple of its size).
+// HBM stores below a 64-byte granule cost a read-modify-write (measured at
+// r = 16: the write pass stores 4.2x the gasket's bytes in 32-byte granules
+// and 5.6x in 64-byte ones, yet takes 82.7 us against 49 us), and sparse reads
+// run fastest as whole 128-byte lines.  The strip kernels store every granule
+// of the largest size a tile row spans (64 bytes, or the 32-byte row of a
+// rho = 32 u8 tile) that holds a gasket cell in full (0 on its off-gasket
+// cells), and load every 128-byte line (or the whole row, if shorter) that
+// holds one.  A granule that holds a gasket cell is exactly one whose first
+// cell does: x0 & y == 0 for a granule starting at x0 (a multiple of its size).
 template <int ROW_BYTES>
 struct Granules {
-  static constexpr int STORE = ROW_BYTES >= 64 ? 64 : 16;
+  static constexpr int STORE = ROW_BYTES >= 64 ? 64 : (ROW_BYTES >= 32 ? 32 : 16);
   static constexpr int LOAD = ROW_BYTES >= 128 ? 128 : (ROW_BYTES >= 64 ? 64 : 16);
 };
 
