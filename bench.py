@@ -360,7 +360,31 @@ def bench_serving(torch, sg, inputs, qps_list, count, cap_gb, horizon_cells=None
             "budget_cells": budget_cells, "by_qps": results}
 
 
-EXTRA_LEGS = ("sweep", "diffusion", "batched", "fractals", "serving")
+def bench_compact_large(torch, sg, r, rho, steps):
+    """Life on a gasket whose embedding cannot exist (2^(2r) bytes): the
+    block-compacted state (3^(r-k) tiles of rho^2 bytes) written on the device
+    from the counter-based Bernoulli(0.5) generator, then `steps` generations
+    at 32 per pass; timed after one warm-up call."""
+    size = sg.sg_compact_bytes(r, rho)
+    a = torch.empty(size, dtype=torch.uint8, device="cuda")
+    out, work = torch.empty_like(a), torch.empty_like(a)
+    init_ms = time_region(torch, lambda: sg.sg_compact_init_bernoulli(r, rho, SEED, 0.5, a), 1, 1)
+    ms = time_region(torch, lambda: sg.sg_ca_steps_compact(r, rho, steps, a, out, work), 1, 1)
+    cells = 3 ** r
+    us = ms * 1e3 / steps
+    frac = CA_BYTES_PER_CELL * cells / (us * 1e-6) / (PEAK_HBM_GBS * 1e9)
+    log(f"compact r={r} rho={rho}: {3 * size / 1e9:.1f} GB of states, init {init_ms:.2f} ms, "
+        f"{us:.1f} us/gen, {cells / (us * 1e-6) / 1e12:.2f} Tcells/s ({frac:.2f} of HBM peak in "
+        f"algorithmic bytes)")
+    del a, out, work
+    torch.cuda.empty_cache()
+    return {"r": r, "rho": rho, "cells": cells, "state_gb": round(size / 1e9, 2),
+            "embedding_bytes": 1 << (2 * r), "init_ms": round(init_ms, 3), "steps": steps,
+            "us_per_step": round(us, 2), "cells_per_s": cells / (us * 1e-6),
+            "hbm_frac_algorithmic": round(frac, 4)}
+
+
+EXTRA_LEGS = ("sweep", "diffusion", "batched", "fractals", "serving", "compact_r20")
 
 
 def main():
@@ -533,6 +557,8 @@ def main():
     if "fractals" in legs:
         extras["other_fractals"] = bench_fractals(torch, sg, 10, 20)
         torch.cuda.empty_cache()
+    if "compact_r20" in legs:
+        extras["compact_r20"] = bench_compact_large(torch, sg, 20, 256, 64)
     if "serving" in legs:
         extras["serving"] = bench_serving(torch, sg, inputs, args.serve_qps, args.serve_requests,
                                           200.0, int(args.serve_horizon) or None,

@@ -203,6 +203,18 @@ SG_API int sg_compact_pack(int r, int rho, const uint8_t *d_dense, uint8_t *d_co
 SG_API int sg_compact_unpack(int r, int rho, const uint8_t *d_compact, uint8_t *d_dense,
                              void *stream);
 
+/* A seeded Bernoulli life state written straight into a compact state
+ * (sg_compact_bytes bytes, 16-byte aligned), for gaskets whose embedding is
+ * too large to build (at r = 20 it would take 2^40 bytes; the compact state
+ * at rho = 256 takes 35 GB).  Gasket cell (x, y) is 1 iff output number
+ * y * 2^32 + x (from 0) of the SplitMix64 generator seeded with `seed`
+ * (Steele, Lea and Flood, OOPSLA 2014) is below `threshold` (so each cell is
+ * alive with probability threshold / 2^64); every other byte is 0.  The same
+ * state as sg_compact_pack of an embedding built that way.
+ * Errors: SG_EINVAL (shape, rho not 64/128/256, NULL or misaligned), SG_EHIP. */
+SG_API int sg_compact_init_bernoulli(int r, int rho, uint64_t seed, uint64_t threshold,
+                                     uint8_t *d_compact, void *stream);
+
 /* sg_ca_steps on compact states (lambda map): `steps` life generations
  * from d_in into d_out, up to `steps_per_pass` (1..32, 0 = 32) per pass;
  * every pass rewrites its output tiles whole, so d_out and d_work need no

@@ -43,6 +43,7 @@ def _load():
         "sgo_life_step_plain": (None, [_i64, _i64, _ptr, _ptr]),
         "sgo_life_step": (None, [_int, _ptr, _ptr]),
         "sgo_life_window": (None, [_int, _ptr, _i64, _i64, _i64, _i64, _int, _ptr]),
+        "sgo_life_region": (None, [_i64, _i64, _i64, _i64, _int, _ptr]),
         "sgo_row_checksums": (None, [_int, _ptr, _ptr, _ptr]),
         "sgo_diffuse_step": (None, [_int, _ptr, _ptr, ctypes.c_double]),
         "sgo_diffuse_window": (None, [_int, _ptr, _i64, _i64, _i64, _i64, _int,
@@ -189,6 +190,17 @@ def life_window(r: int, a: np.ndarray, x0: int, y0: int, w: int, h: int,
     a = _check_state(r, a, np.uint8)
     out = np.zeros((h, w), dtype=np.uint8)
     _load().sgo_life_window(r, _p(a), x0, y0, w, h, steps, _p(out))
+    return out
+
+
+def life_region(gx0: int, gy0: int, a: np.ndarray, steps: int) -> np.ndarray:
+    """`steps` gasket life steps on the region of the grid whose top-left cell
+    is (gx0, gy0), held in `a`, with every cell outside it taken as dead (the
+    region must lie inside the grid; cells within Chebyshev distance `steps`
+    of an edge where the region is cut short of the grid's come out wrong)."""
+    out = np.ascontiguousarray(a, dtype=np.uint8).copy()
+    h, w = out.shape
+    _load().sgo_life_region(gx0, gy0, w, h, steps, _p(out))
     return out
 
 

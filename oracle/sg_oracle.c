@@ -213,6 +213,42 @@ void sgo_life_step(int r, const uint8_t *in, uint8_t *out)
         }
 }
 
+/* `steps` gasket life steps applied to a region of the grid: the gw x gh
+ * cells whose top-left cell is (gx0, gy0), held row-major in `a` and updated
+ * in place, with every cell outside the region taken as dead.  The region
+ * must lie inside the grid (its edges there are the grid's real boundary);
+ * where it is cut short of the grid's edge, the cells within Chebyshev
+ * distance `steps` of the cut come out wrong. */
+void sgo_life_region(int64_t gx0, int64_t gy0, int64_t gw, int64_t gh, int steps, uint8_t *a)
+{
+    uint8_t *b = (uint8_t *)malloc((size_t)(gw * gh));
+    uint8_t *cur = a, *nxt = b;
+    for (int t = 0; t < steps; ++t) {
+        for (int64_t y = 0; y < gh; ++y)
+            for (int64_t x = 0; x < gw; ++x) {
+                int64_t X = gx0 + x, Y = gy0 + y;
+                if (!sgo_member(X, Y)) {
+                    nxt[y * gw + x] = 0;
+                    continue;
+                }
+                int c = 0;
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        int64_t xx = x + dx, yy = y + dy;
+                        if ((dx || dy) && xx >= 0 && xx < gw && yy >= 0 && yy < gh &&
+                            sgo_member(gx0 + xx, gy0 + yy))
+                            c += cur[yy * gw + xx] != 0;
+                    }
+                int self = cur[y * gw + x] != 0;
+                nxt[y * gw + x] = (uint8_t)(c == 3 || (self && c == 2));
+            }
+        uint8_t *s = cur; cur = nxt; nxt = s;
+    }
+    if (cur != a)
+        memcpy(a, cur, (size_t)(gw * gh));
+    free(b);
+}
+
 /* `steps` gasket life steps evaluated on the window [x0, x0+w) x [y0, y0+h)
  * of a full n x n state.  A cell after t steps depends only on cells within
  * Chebyshev distance t, so the window grown by `steps` on every side (and
@@ -230,34 +266,12 @@ void sgo_life_window(int r, const uint8_t *in, int64_t x0, int64_t y0,
     int64_t gy1 = y0 + h + steps > n ? n : y0 + h + steps;
     int64_t gw = gx1 - gx0, gh = gy1 - gy0;
     uint8_t *a = (uint8_t *)malloc((size_t)(gw * gh));
-    uint8_t *b = (uint8_t *)malloc((size_t)(gw * gh));
     for (int64_t y = 0; y < gh; ++y)
         memcpy(a + y * gw, in + (gy0 + y) * n + gx0, (size_t)gw);
-    for (int t = 0; t < steps; ++t) {
-        for (int64_t y = 0; y < gh; ++y)
-            for (int64_t x = 0; x < gw; ++x) {
-                int64_t X = gx0 + x, Y = gy0 + y;
-                if (!sgo_member(X, Y)) {
-                    b[y * gw + x] = 0;
-                    continue;
-                }
-                int c = 0;
-                for (int dy = -1; dy <= 1; ++dy)
-                    for (int dx = -1; dx <= 1; ++dx) {
-                        int64_t xx = x + dx, yy = y + dy;
-                        if ((dx || dy) && xx >= 0 && xx < gw && yy >= 0 && yy < gh &&
-                            sgo_member(gx0 + xx, gy0 + yy))
-                            c += a[yy * gw + xx] != 0;
-                    }
-                int self = a[y * gw + x] != 0;
-                b[y * gw + x] = (uint8_t)(c == 3 || (self && c == 2));
-            }
-        uint8_t *s = a; a = b; b = s;
-    }
+    sgo_life_region(gx0, gy0, gw, gh, steps, a);
     for (int64_t y = 0; y < h; ++y)
         memcpy(out + y * w, a + (y0 - gy0 + y) * gw + (x0 - gx0), (size_t)w);
     free(a);
-    free(b);
 }
 
 /* Per-row checksums of a u8 state: xr[y] = XOR over the row, pop[y] = sum of

@@ -258,6 +258,16 @@ int compact_copy(int r, int rho, const uint8_t *src, uint8_t *dst, bool pack, vo
 }
 }  // namespace
 
+SG_API int sg_compact_init_bernoulli(int r, int rho, uint64_t seed, uint64_t threshold,
+                                     uint8_t *d_compact, void *stream) {
+  sg::PassArgs a;
+  const int st = pass_args(SG_MAP_LAMBDA, r, rho, stream, a);
+  if (st != SG_OK) return st;
+  if (!sg::life_tb_supported(rho) || !d_compact || misaligned(d_compact)) return SG_EINVAL;
+  SG_INJECT();
+  return hip_status(sg::launch_compact_init(a, seed, threshold, d_compact));
+}
+
 SG_API int sg_compact_pack(int r, int rho, const uint8_t *d_dense, uint8_t *d_compact,
                            void *stream) {
   return compact_copy(r, rho, d_dense, d_compact, true, stream);

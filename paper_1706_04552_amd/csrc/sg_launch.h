@@ -44,6 +44,8 @@ hipError_t launch_life_tb(const PassArgs &a, int T, const uint8_t *in, uint8_t *
 // Block-compacted storage (tiles of side rho in {64, 128, 256}, lambda order).
 hipError_t launch_map_lambda_inverse(int rb, int32_t *d_out, hipStream_t s);
 hipError_t launch_compact_copy(const PassArgs &a, bool pack, const uint8_t *src, uint8_t *dst);
+hipError_t launch_compact_init(const PassArgs &a, uint64_t seed, uint64_t threshold,
+                               uint8_t *dst);
 hipError_t launch_life_tb_compact(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
 
 // Temporally blocked FP32 diffusion: T steps per pass, T in

@@ -8,6 +8,12 @@ every other cell of the n x n embedding holds 0.
 Draw order: one draw per gasket cell, in row-major order, from NumPy's
 ``default_rng(seed)`` (PCG64).  Rows are filled in chunks, which does not change
 the stream: consecutive calls of ``Generator.random`` continue it.
+
+States too large to build on the host (r > 16) use a counter-based generator
+instead, so that any cell's value can be computed on its own: cell (x, y) takes
+output number y * 2^32 + x of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014)
+seeded with the seed, and is alive iff that output is below a threshold.  The
+library's sg_compact_init_bernoulli writes the same state on the device.
 """
 from dataclasses import dataclass
 from typing import List
@@ -130,3 +136,48 @@ def poisson_requests(qps: float, count: int, r_lo: int = 8, r_hi: int = 15,
     st = rng.integers(steps_lo, steps_hi + 1, size=count)
     return [RequestSpec(i, float(t[i]), int(rs[i]), int(st[i]), seed + 1000 + i)
             for i in range(count)]
+
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_MIX1 = np.uint64(0xBF58476D1CE4E5B9)
+_MIX2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64_at(seed: int, counters) -> np.ndarray:
+    """Outputs number `counters` (from 0) of SplitMix64 seeded with `seed`:
+    the seed plus (c + 1) golden-ratio gammas, through the generator's
+    finaliser; uint64, arithmetic modulo 2^64."""
+    c = np.asarray(counters, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed & ((1 << 64) - 1)) + (c + np.uint64(1)) * _GAMMA
+        z = (z ^ (z >> np.uint64(30))) * _MIX1
+        z = (z ^ (z >> np.uint64(27))) * _MIX2
+    return z ^ (z >> np.uint64(31))
+
+
+def counter_threshold(p: float) -> int:
+    """The uint64 threshold under which an output makes a cell alive with
+    probability p."""
+    return min(int(p * 2.0 ** 64), (1 << 64) - 1)
+
+
+def counter_region(r: int, x0: int, y0: int, w: int, h: int, p: float = 0.5,
+                   seed: int = DEFAULT_SEED) -> np.ndarray:
+    """uint8 h x w block of the counter-based state at columns x0.. and rows
+    y0..: 1 on the gasket cells whose output is below the threshold, 0 on the
+    other cells and outside the n x n grid."""
+    n = 1 << r
+    x = np.arange(x0, x0 + w, dtype=np.int64)[None, :]
+    y = np.arange(y0, y0 + h, dtype=np.int64)[:, None]
+    inside = (x >= 0) & (x < n) & (y >= 0) & (y < n)
+    xs, ys = np.clip(x, 0, n - 1), np.clip(y, 0, n - 1)
+    on = inside & ((xs & ys) == 0)
+    ctr = (ys.astype(np.uint64) << np.uint64(32)) | xs.astype(np.uint64)
+    alive = splitmix64_at(seed, ctr) < np.uint64(counter_threshold(p))
+    return (on & alive).astype(np.uint8)
+
+
+def counter_state(r: int, p: float = 0.5, seed: int = DEFAULT_SEED) -> np.ndarray:
+    """The whole n x n counter-based state (small r only)."""
+    n = 1 << r
+    return counter_region(r, 0, 0, n, n, p, seed)

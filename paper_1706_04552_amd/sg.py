@@ -98,6 +98,8 @@ _SIGNATURES = {
     "sg_map_lambda_inverse": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                              ctypes.c_void_p]),
     "sg_compact_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _u64p]),
+    "sg_compact_init_bernoulli": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                                  ctypes.c_uint64, _vp, _vp]),
     "sg_compact_pack": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p]),
     "sg_compact_unpack": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
@@ -326,6 +328,22 @@ def sg_compact_bytes(r: int, rho: int) -> int:
     b = ctypes.c_uint64()
     _check(load().sg_compact_bytes(r, rho, ctypes.byref(b)), "sg_compact_bytes")
     return b.value
+
+
+def bernoulli_threshold(p: float) -> int:
+    """The uint64 threshold under which a SplitMix64 output makes a cell alive
+    with probability p."""
+    if not 0.0 <= p <= 1.0:
+        raise ValueError(f"p={p} outside [0, 1]")
+    return min(int(p * 2.0 ** 64), (1 << 64) - 1)
+
+
+def sg_compact_init_bernoulli(r: int, rho: int, seed: int, p: float, d_compact: torch.Tensor,
+                              stream=None) -> torch.Tensor:
+    pc = _dev(d_compact, torch.uint8, sg_compact_bytes(r, rho), "d_compact")
+    _check(load().sg_compact_init_bernoulli(r, rho, seed & ((1 << 64) - 1), bernoulli_threshold(p),
+                                            pc, _stream(stream)), "sg_compact_init_bernoulli")
+    return d_compact
 
 
 def sg_compact_pack(r: int, rho: int, d_dense: torch.Tensor, d_compact: torch.Tensor,

@@ -205,6 +205,7 @@ a, b, w = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x7000000000), ctypes.c_voi
 res = [lib.sg_ca_step(0, 8, 16, a, b, None), lib.sg_write_pass(1, 8, 16, a, 1, None),
        lib.sg_diffuse_step(0, 8, 16, a, b, 0.2, None), lib.sg_map_lambda(8, 16, a, None),
        lib.sg_map_bbox(8, 16, a, None), lib.sg_ca_steps(0, 8, 64, 20, 16, a, b, w, None),
+       lib.sg_compact_init_bernoulli(8, 64, 1, 1 << 63, a, None),
        lib.sg_ca_step(0, 8, 3, a, b, None)]
 print(res, lib.sg_last_hip_error().decode())
 """ % ROOT
@@ -214,7 +215,7 @@ print(res, lib.sg_last_hip_error().decode())
     assert out.returncode == 0, out.stderr
     line = out.stdout.strip().splitlines()[-1]
     res = eval(line.split("]")[0] + "]")
-    assert res[:6] == [-3] * 6 and res[6] == -1  # invalid arguments are still SG_EINVAL
+    assert res[:7] == [-3] * 7 and res[7] == -1  # invalid arguments are still SG_EINVAL
     assert line.split("]", 1)[1].strip()  # the HIP error text is kept
 
 
@@ -273,6 +274,12 @@ def test_compact_storage_validation(lib):
                                    w, None) == sg.SG_EALIAS
     assert lib.sg_ca_steps_compact(r, rho, 17, 16, a, b, ctypes.c_void_p(0x7000000000 + 16),
                                    None) == sg.SG_EALIAS
+    # the device-written initial state: tile sides and shapes as above, an aligned array
+    for rr, rr_rho in ((r, 32), (5, 64), (21, 256), (10, 512)):
+        assert lib.sg_compact_init_bernoulli(rr, rr_rho, 1, 1 << 63, comp, None) == sg.SG_EINVAL
+    assert lib.sg_compact_init_bernoulli(r, rho, 1, 1 << 63, None, None) == sg.SG_EINVAL
+    assert lib.sg_compact_init_bernoulli(r, rho, 1, 1 << 63, ctypes.c_void_p(0x7000000004),
+                                         None) == sg.SG_EINVAL
     # the inverse map: omega must fit an int32, the output array 4-byte aligned
     assert lib.sg_map_lambda_inverse(r, rho, None, None) == sg.SG_EINVAL
     assert lib.sg_map_lambda_inverse(r, rho, ctypes.c_void_p(0x100002), None) == sg.SG_EINVAL

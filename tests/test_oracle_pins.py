@@ -497,3 +497,52 @@ def test_rect_map_is_a_bijection_onto_the_live_blocks(r, rho_x, rho_y):
 def test_rect_map_with_square_blocks_is_lambda(r, rho):
     rb = r - (rho.bit_length() - 1)
     assert np.array_equal(O.map_lambda_rect(r, rho, rho), O.map_lambda(rb))
+
+
+# ------------------------------------------------------------------ counter-based inputs
+
+def test_splitmix64_reference_outputs():
+    # the first outputs of SplitMix64 for seeds 0 and 1234567, as published
+    # with the generator's reference implementation
+    assert [int(v) for v in inputs.splitmix64_at(0, [0, 1, 2])] == [
+        0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert [int(v) for v in inputs.splitmix64_at(1234567, [0, 1, 2])] == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423]
+
+
+@pytest.mark.parametrize("p", [0.0, 0.25, 0.5, 1.0])
+def test_counter_state_is_bernoulli_on_the_gasket(p):
+    r = 9
+    a = inputs.counter_state(r, p, seed=11)
+    n = 1 << r
+    on = (np.arange(n)[None, :] & np.arange(n)[:, None]) == 0
+    assert not a[~on].any()
+    k = int(a.sum())
+    if p in (0.0, 1.0):
+        assert k == int(p) * 3 ** r
+    else:  # within 5 standard deviations of the binomial mean
+        mu, sd = p * 3 ** r, (p * (1 - p) * 3 ** r) ** 0.5
+        assert abs(k - mu) < 5 * sd
+    # any block is the same slice of the whole state, also across the grid edge
+    assert np.array_equal(inputs.counter_region(r, 100, 37, 50, 20, p, 11), a[37:57, 100:150])
+    edge = inputs.counter_region(r, n - 5, -3, 10, 8, p, 11)
+    assert not edge[:3].any() and not edge[:, 5:].any()
+    assert np.array_equal(edge[3:, :5], a[0:5, n - 5:])
+
+
+@pytest.mark.parametrize("r,steps", [(7, 9), (9, 15)])
+def test_life_region_equals_full_run(r, steps):
+    # the oracle's region evolution, given only a window's dependency cone,
+    # against the whole state run step by step
+    a0 = inputs.counter_state(r, 0.5, seed=3)
+    full = O.life_steps(r, a0, steps)
+    n = 1 << r
+    rng = np.random.default_rng(5)
+    boxes = [(0, 0, 16, 8), (n - 16, n - 8, 16, 8), (n // 2 - 7, 3, 20, 10)]
+    boxes += [(int(rng.integers(0, n - 12)), int(rng.integers(0, n - 12)), 12, 12) for _ in range(4)]
+    for x0, y0, w, h in boxes:
+        gx0, gy0 = max(0, x0 - steps), max(0, y0 - steps)
+        gx1, gy1 = min(n, x0 + w + steps), min(n, y0 + h + steps)
+        reg = O.life_region(gx0, gy0, a0[gy0:gy1, gx0:gx1], steps)
+        assert np.array_equal(reg[y0 - gy0:y0 - gy0 + h, x0 - gx0:x0 - gx0 + w],
+                              full[y0:y0 + h, x0:x0 + w]), (x0, y0)
