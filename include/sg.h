@@ -437,8 +437,10 @@ SG_API int sg_server_create(const sg_tune *tune, uint64_t cap_bytes, int max_req
 SG_API int sg_server_reserve(sg_server *s, const int32_t *levels, int count);
 
 /* Queues a request: `steps` generations of the level-r gasket (r 6..SG_MAX_R)
- * from d_init (device, n x n, 16-byte aligned, 0 off the gasket; read when
- * the request is admitted, so it must stay valid until then).  d_out: NULL,
+ * from d_init (device, n x n, 16-byte aligned, 0 off the gasket).  d_init is
+ * copied when a round admits the request, which the server does not report,
+ * so it must stay valid and unchanged until the request is reported done or
+ * rejected.  d_out: NULL,
  * or a device n x n buffer (16-byte aligned) that receives a copy of the
  * result before the round that finishes the request returns.
  * Errors: SG_EINVAL, SG_ENOMEM (max_requests reached). */
