@@ -122,6 +122,28 @@ def test_write_pass_exact(map_kind, r, rho):
         assert np.array_equal(a.cpu().numpy(), O.write_pass(r, v))
 
 
+@pytest.fixture(scope="module")
+def write_pass_r16():
+    """The oracle's r = 16 write pass (value 1), on the device: 4 GiB."""
+    ref = torch.from_numpy(O.write_pass(16, 1)).cuda()
+    yield ref
+    del ref
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
+@pytest.mark.parametrize("rho", [1, 4, 16, 32, 64, 256])
+def test_write_pass_full_size_exact(write_pass_r16, map_kind, rho):
+    # the paper's experiment at n = 2^16, every element against the oracle,
+    # in the launch configurations the benchmark times
+    note(f"write_pass full size {map_kind} r=16 rho={rho}")
+    a = torch.zeros((1 << 16, 1 << 16), dtype=torch.uint8, device="cuda")
+    sg.sg_write_pass(map_kind, 16, rho, a, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, write_pass_r16)
+    del a
+
+
 @pytest.mark.parametrize("intra", ["unroll", "lut", "subbox"])
 @pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
 @pytest.mark.parametrize("r,rho", cases([0, 1, 3, 6, 9, 11], [1, 2, 4, 8, 16, 32]))
