@@ -247,6 +247,28 @@ def test_ca_steps_exact(map_kind, r, rho, steps, spp):
 
 
 
+@pytest.fixture(scope="module")
+def life_r16_36():
+    """The benchmark's r = 16 initial state and the oracle's state 36
+    generations later (dense C oracle, about 20 s on 16 cores), on the device."""
+    a0 = inputs.bernoulli_state(16, 0.5, 1706)
+    ref = torch.from_numpy(O.life_steps(16, a0, 36)).cuda()
+    yield a0, ref
+    del ref
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("map_kind,rho", [("lambda", 256), ("bbox", 256), ("lambda", 128)])
+def test_ca_steps_full_size_exact(life_r16_36, map_kind, rho):
+    # every cell of the r = 16 state after one 32-generation pass and one
+    # 4-generation pass: the benchmark's launch configuration
+    a0, ref = life_r16_36
+    note(f"ca_steps full size exact {map_kind} r=16 rho={rho} 36 steps, 32 per pass")
+    got = gpu_ca_steps(map_kind, 16, rho, a0, 36, 32)
+    assert torch.equal(got, ref)
+    del got
+
+
 @pytest.mark.parametrize("r,rho,spp", [(16, 256, 16), (16, 256, 32), (16, 128, 16), (14, 64, 32)])
 def test_ca_steps_full_size_sampled(r, rho, spp):
     steps = 100
