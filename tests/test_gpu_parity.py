@@ -352,6 +352,25 @@ def test_diffuse_steps_equal_one_step_calls_and_oracle(map_kind, rho, r, steps, 
     assert max_abs <= DIFF_RTOL * scale and rel_l2 <= DIFF_RTOL
 
 
+@pytest.mark.parametrize("map_kind,rho", [("lambda", 32), ("bbox", 32), ("lambda", 64)])
+def test_diffuse_steps_full_size_all_cells(map_kind, rho):
+    # every cell of the r = 14 field after two 8-step passes (the benchmark's
+    # launch configuration) against the FP64 oracle, at the stated tolerance
+    r, steps = 14, 16
+    note(f"diffuse_steps full size, all cells {map_kind} r={r} rho={rho} {steps} steps")
+    u0 = inputs.uniform_field(r, 1706)
+    a = dev(u0)
+    out, work = torch.zeros_like(a), torch.zeros_like(a)
+    sg.sg_diffuse_steps(map_kind, r, rho, steps, a, out, work, 0.2, steps_per_pass=8)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    del a, out, work
+    ref = O.diffuse_steps(r, u0, steps)
+    max_abs, scale, rel_l2 = diff_errors(got, ref)
+    note(f"  max_abs={max_abs:.3e} scale={scale:.3e} rel_l2={rel_l2:.3e}")
+    assert max_abs <= DIFF_RTOL * scale and rel_l2 <= DIFF_RTOL
+
+
 @pytest.mark.parametrize("rho", [32, 64])
 def test_diffuse_steps_full_size_sampled(rho):
     r, steps = 14, 500
