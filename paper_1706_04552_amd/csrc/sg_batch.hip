@@ -10,7 +10,9 @@
 
 #include <algorithm>
 #include <map>
+#include <memory>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "../../include/sg.h"
@@ -205,6 +207,20 @@ struct sg_pass_ctx {
   bool pending[kPassRing] = {};
 };
 
+
+namespace {
+// C entry points report an allocation failure inside them as SG_ENOMEM
+// rather than letting the exception cross the C ABI.
+template <class F>
+int guarded(F &&f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc &) {
+    return SG_ENOMEM;
+  }
+}
+}  // namespace
+
 extern "C" {
 
 SG_API int sg_tune_default(sg_tune *t) {
@@ -218,37 +234,36 @@ SG_API int sg_tune_default(sg_tune *t) {
 
 SG_API int sg_batch_create(const sg_gasket *gaskets, int count, const sg_tune *tune,
                            sg_batch **out) {
-  if (!out) return SG_EINVAL;
-  *out = nullptr;
-  int st = check_tune(tune);
-  if (st != SG_OK) return st;
-  sg_batch *b = new sg_batch();
-  b->tune = *tune;
-  b->gaskets.assign(gaskets ? gaskets : nullptr, gaskets ? gaskets + std::max(count, 0) : nullptr);
-  st = make_plan(b->gaskets.data(), count, b->tune, b->plan);
-  if (st == SG_OK) st = upload_plan(b->plan, &b->d_tables, b->offsets);
-  if (st == SG_OK && cu_count() <= 0) st = SG_EHIP;  // query the device before capturing
-  if (st == SG_OK) {
-    // capture every pass into one graph on a private stream
-    hipStream_t cs = nullptr;
-    st = hip_err(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  return guarded([&]() -> int {
+    if (!out) return SG_EINVAL;
+    *out = nullptr;
+    int st = check_tune(tune);
+    if (st != SG_OK) return st;
+    std::unique_ptr<sg_batch, void (*)(sg_batch *)> b(new sg_batch(), sg_batch_destroy);
+    b->tune = *tune;
+    b->gaskets.assign(gaskets ? gaskets : nullptr, gaskets ? gaskets + std::max(count, 0) : nullptr);
+    st = make_plan(b->gaskets.data(), count, b->tune, b->plan);
+    if (st == SG_OK) st = upload_plan(b->plan, &b->d_tables, b->offsets);
+    if (st == SG_OK && cu_count() <= 0) st = SG_EHIP;  // query the device before capturing
     if (st == SG_OK) {
-      st = hip_err(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      // capture every pass into one graph on a private stream
+      hipStream_t cs = nullptr;
+      st = hip_err(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
       if (st == SG_OK) {
-        const int lst = launch_plan(b->plan, b->tune, b->d_tables, b->offsets, cs);
-        const hipError_t ec = hipStreamEndCapture(cs, &b->graph);
-        st = lst != SG_OK ? lst : hip_err(ec);
+        st = hip_err(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        if (st == SG_OK) {
+          const int lst = launch_plan(b->plan, b->tune, b->d_tables, b->offsets, cs);
+          const hipError_t ec = hipStreamEndCapture(cs, &b->graph);
+          st = lst != SG_OK ? lst : hip_err(ec);
+        }
+        if (st == SG_OK) st = hip_err(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        (void)hipStreamDestroy(cs);
       }
-      if (st == SG_OK) st = hip_err(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
-      (void)hipStreamDestroy(cs);
     }
-  }
-  if (st != SG_OK) {
-    sg_batch_destroy(b);
-    return st;
-  }
-  *out = b;
-  return SG_OK;
+    if (st != SG_OK) return st;  // the batch is destroyed on the way out
+    *out = b.release();
+    return SG_OK;
+  });
 }
 
 SG_API int sg_batch_run(sg_batch *b, void *stream) {
@@ -280,126 +295,132 @@ SG_API void sg_batch_destroy(sg_batch *b) {
 
 SG_API int sg_batch_autotune(const sg_gasket *gaskets, int count, sg_tune *best,
                              float *best_ms, void *stream) {
-  if (!best) return SG_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    if (e0) (void)hipEventDestroy(e0);
-    return SG_EHIP;
-  }
-  float best_t = -1.0f;
-  int st_any = SG_EINVAL;
-  const int rhos[] = {64, 128, 256}, spps[] = {8, 16, 32}, gpcs[] = {0, 2, 4, 8}, thr[] = {256, 512};
-  for (int rho : rhos) {
-    for (int spp : spps)
-      for (int gpc : gpcs)
-        for (int th : thr) {
-          sg_tune t{rho, spp, gpc, th};
-          Plan plan;
-          int st = make_plan(gaskets, count, t, plan);
-          if (st != SG_OK) {
-            st_any = st;
-            continue;
+  return guarded([&]() -> int {
+    if (!best) return SG_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (e0) (void)hipEventDestroy(e0);
+      return SG_EHIP;
+    }
+    float best_t = -1.0f;
+    int st_any = SG_EINVAL;
+    const int rhos[] = {64, 128, 256}, spps[] = {8, 16, 32}, gpcs[] = {0, 2, 4, 8}, thr[] = {256, 512};
+    for (int rho : rhos) {
+      for (int spp : spps)
+        for (int gpc : gpcs)
+          for (int th : thr) {
+            sg_tune t{rho, spp, gpc, th};
+            Plan plan;
+            int st = make_plan(gaskets, count, t, plan);
+            if (st != SG_OK) {
+              st_any = st;
+              continue;
+            }
+            sg::BatchItem *d = nullptr;
+            std::vector<size_t> off;
+            st = upload_plan(plan, &d, off);
+            float ms = 0.0f;
+            if (st == SG_OK) st = launch_plan(plan, t, d, off, s);  // warm-up
+            if (st == SG_OK) st = hip_err(hipEventRecord(e0, s));
+            if (st == SG_OK) st = launch_plan(plan, t, d, off, s);
+            if (st == SG_OK) st = hip_err(hipEventRecord(e1, s));
+            if (st == SG_OK) st = hip_err(hipEventSynchronize(e1));
+            if (st == SG_OK) st = hip_err(hipEventElapsedTime(&ms, e0, e1));
+            if (d) (void)hipFree(d);
+            if (st != SG_OK) {
+              (void)hipEventDestroy(e0);
+              (void)hipEventDestroy(e1);
+              return st;
+            }
+            st_any = SG_OK;
+            if (best_t < 0.0f || ms < best_t) {
+              best_t = ms;
+              *best = t;
+            }
           }
-          sg::BatchItem *d = nullptr;
-          std::vector<size_t> off;
-          st = upload_plan(plan, &d, off);
-          float ms = 0.0f;
-          if (st == SG_OK) st = launch_plan(plan, t, d, off, s);  // warm-up
-          if (st == SG_OK) st = hip_err(hipEventRecord(e0, s));
-          if (st == SG_OK) st = launch_plan(plan, t, d, off, s);
-          if (st == SG_OK) st = hip_err(hipEventRecord(e1, s));
-          if (st == SG_OK) st = hip_err(hipEventSynchronize(e1));
-          if (st == SG_OK) st = hip_err(hipEventElapsedTime(&ms, e0, e1));
-          if (d) (void)hipFree(d);
-          if (st != SG_OK) {
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            return st;
-          }
-          st_any = SG_OK;
-          if (best_t < 0.0f || ms < best_t) {
-            best_t = ms;
-            *best = t;
-          }
-        }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (best_t < 0.0f) return st_any;
-  if (best_ms) *best_ms = best_t;
-  return SG_OK;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (best_t < 0.0f) return st_any;
+    if (best_ms) *best_ms = best_t;
+    return SG_OK;
+  });
 }
 
 SG_API int sg_pass_ctx_create(int capacity, sg_pass_ctx **out) {
-  if (!out || capacity < 1 || capacity > (1 << 24)) return SG_EINVAL;
-  *out = nullptr;
-  sg_pass_ctx *c = new sg_pass_ctx();
-  c->capacity = capacity;
-  const size_t bytes = (size_t)kPassRing * (size_t)capacity * sizeof(sg::BatchItem);
-  int st = SG_OK;
-  if (hipMalloc((void **)&c->d_items, bytes) != hipSuccess) st = SG_ENOMEM;
-  if (st == SG_OK && hipHostMalloc((void **)&c->h_stage, bytes, hipHostMallocDefault) != hipSuccess)
-    st = SG_ENOMEM;
-  for (int k = 0; k < kPassRing && st == SG_OK; ++k)
-    st = hip_err(hipEventCreateWithFlags(&c->staged[k], hipEventDisableTiming));
-  if (st != SG_OK) {
-    sg_pass_ctx_destroy(c);
-    return st;
-  }
-  *out = c;
-  return SG_OK;
+  return guarded([&]() -> int {
+    if (!out || capacity < 1 || capacity > (1 << 24)) return SG_EINVAL;
+    *out = nullptr;
+    sg_pass_ctx *c = new sg_pass_ctx();
+    c->capacity = capacity;
+    const size_t bytes = (size_t)kPassRing * (size_t)capacity * sizeof(sg::BatchItem);
+    int st = SG_OK;
+    if (hipMalloc((void **)&c->d_items, bytes) != hipSuccess) st = SG_ENOMEM;
+    if (st == SG_OK && hipHostMalloc((void **)&c->h_stage, bytes, hipHostMallocDefault) != hipSuccess)
+      st = SG_ENOMEM;
+    for (int k = 0; k < kPassRing && st == SG_OK; ++k)
+      st = hip_err(hipEventCreateWithFlags(&c->staged[k], hipEventDisableTiming));
+    if (st != SG_OK) {
+      sg_pass_ctx_destroy(c);
+      return st;
+    }
+    *out = c;
+    return SG_OK;
+  });
 }
 
 SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
                        const sg_tune *tune, void *stream) {
-  if (!ctx || count < 0 || count > ctx->capacity || (count > 0 && !items)) return SG_EINVAL;
-  int st = check_tune(tune);
-  if (st != SG_OK) return st;
-  const int kmax = rho_log2(tune->rho);
-  // validate everything before touching the staging buffer or the device
-  int live = 0, max_steps = 0;
-  for (int i = 0; i < count; ++i) {
-    const sg_pass_item &it = items[i];
-    if (it.steps < 0 || it.steps > tune->steps_per_pass) return SG_EINVAL;
-    if (it.steps == 0) continue;
-    if (it.r < kMinTileLog2 || it.r > SG_MAX_R || !it.src || !it.dst) return SG_EINVAL;
-    if (misaligned(it.src) || misaligned(it.dst)) return SG_EINVAL;
-    if (overlaps(it.src, it.dst, ((size_t)1 << it.r) * ((size_t)1 << it.r))) return SG_EALIAS;
-    ++live;
-    max_steps = std::max(max_steps, (int)it.steps);
-  }
-  if (live == 0) return SG_OK;
-  if (sg::inject_hip_error()) return SG_EHIP;
-  hipStream_t s = (hipStream_t)stream;
-  const int slot = ctx->next;
-  if (ctx->pending[slot] && hipEventSynchronize(ctx->staged[slot]) != hipSuccess) return SG_EHIP;
-  sg::BatchItem *h_stage = ctx->h_stage + (size_t)slot * ctx->capacity;
-  sg::BatchItem *d_items = ctx->d_items + (size_t)slot * ctx->capacity;
-  uint64_t tiles = 0;
-  int m = 0;
-  for (int i = 0; i < count; ++i) {
-    const sg_pass_item &it = items[i];
-    if (it.steps == 0) continue;
-    sg::BatchItem b;
-    b.src = it.src;
-    b.dst = it.dst;
-    b.r = it.r;
-    b.steps = (int16_t)it.steps;
-    b.k = (int16_t)item_k(it.r, kmax);
-    b.tile_begin = tiles;
-    tiles += pow3(it.r - b.k);
-    h_stage[m++] = b;
-  }
-  st = hip_err(hipMemcpyAsync(d_items, h_stage, (size_t)m * sizeof(sg::BatchItem),
-                              hipMemcpyHostToDevice, s));
-  if (st != SG_OK) return st;
-  st = hip_err(hipEventRecord(ctx->staged[slot], s));
-  if (st != SG_OK) return st;
-  ctx->pending[slot] = true;
-  ctx->next = (slot + 1) % kPassRing;
-  return hip_err(sg::launch_life_tb_batch(tune->rho, tune->threads, d_items, m, tiles,
-                                          max_steps, groups_for(*tune, tiles), s));
+  return guarded([&]() -> int {
+    if (!ctx || count < 0 || count > ctx->capacity || (count > 0 && !items)) return SG_EINVAL;
+    int st = check_tune(tune);
+    if (st != SG_OK) return st;
+    const int kmax = rho_log2(tune->rho);
+    // validate everything before touching the staging buffer or the device
+    int live = 0, max_steps = 0;
+    for (int i = 0; i < count; ++i) {
+      const sg_pass_item &it = items[i];
+      if (it.steps < 0 || it.steps > tune->steps_per_pass) return SG_EINVAL;
+      if (it.steps == 0) continue;
+      if (it.r < kMinTileLog2 || it.r > SG_MAX_R || !it.src || !it.dst) return SG_EINVAL;
+      if (misaligned(it.src) || misaligned(it.dst)) return SG_EINVAL;
+      if (overlaps(it.src, it.dst, ((size_t)1 << it.r) * ((size_t)1 << it.r))) return SG_EALIAS;
+      ++live;
+      max_steps = std::max(max_steps, (int)it.steps);
+    }
+    if (live == 0) return SG_OK;
+    if (sg::inject_hip_error()) return SG_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    const int slot = ctx->next;
+    if (ctx->pending[slot] && hipEventSynchronize(ctx->staged[slot]) != hipSuccess) return SG_EHIP;
+    sg::BatchItem *h_stage = ctx->h_stage + (size_t)slot * ctx->capacity;
+    sg::BatchItem *d_items = ctx->d_items + (size_t)slot * ctx->capacity;
+    uint64_t tiles = 0;
+    int m = 0;
+    for (int i = 0; i < count; ++i) {
+      const sg_pass_item &it = items[i];
+      if (it.steps == 0) continue;
+      sg::BatchItem b;
+      b.src = it.src;
+      b.dst = it.dst;
+      b.r = it.r;
+      b.steps = (int16_t)it.steps;
+      b.k = (int16_t)item_k(it.r, kmax);
+      b.tile_begin = tiles;
+      tiles += pow3(it.r - b.k);
+      h_stage[m++] = b;
+    }
+    st = hip_err(hipMemcpyAsync(d_items, h_stage, (size_t)m * sizeof(sg::BatchItem),
+                                hipMemcpyHostToDevice, s));
+    if (st != SG_OK) return st;
+    st = hip_err(hipEventRecord(ctx->staged[slot], s));
+    if (st != SG_OK) return st;
+    ctx->pending[slot] = true;
+    ctx->next = (slot + 1) % kPassRing;
+    return hip_err(sg::launch_life_tb_batch(tune->rho, tune->threads, d_items, m, tiles,
+                                            max_steps, groups_for(*tune, tiles), s));
+  });
 }
 
 SG_API void sg_pass_ctx_destroy(sg_pass_ctx *ctx) {
