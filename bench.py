@@ -170,11 +170,11 @@ def bench_diffusion(torch, sg, inputs, rhos, steps, warmup):
             res[map_kind][rho] = ms
             log(f"diffuse r=14 {map_kind:6s} rho={rho:3d}: {ms * 1e3:8.2f} us/step")
             del bufs
-    # temporally blocked: 4 or 8 steps per pass at rho = 32 and 64, over `steps` steps
+    # temporally blocked: 4 or 8 steps per pass at rho = 16, 32 and 64, over `steps` steps
     tb = {"lambda": {}, "bbox": {}}
     Out, Work = torch.zeros_like(U), torch.zeros_like(U)
     for map_kind in ("lambda", "bbox"):
-        for rho in (32, 64):
+        for rho in (16, 32, 64):
             for T in (4, 8):
                 def run():
                     sg.sg_diffuse_steps(map_kind, r, rho, steps, U, Out, Work, 0.2, steps_per_pass=T)

@@ -1,6 +1,6 @@
 // Temporally blocked FP32 diffusion on the gasket (gfx950).
 //
-// One workgroup owns one rho x rho tile (rho in {32, 64}) of the map and
+// One workgroup owns one rho x rho tile (rho in {16, 32, 64}) of the map and
 // advances it by T <= 8 explicit diffusion steps per pass:
 //  1. load the tile plus a halo of T rows above/below and 8 cells left/right
 //     (two float4 chunks) into registers, every load issued before the first
@@ -263,12 +263,13 @@ hipError_t diffuse_tb_rho(const PassArgs &a, int T, const float *in, float *out,
 
 }  // namespace
 
-bool diffuse_tb_supported(int rho) { return rho == 32 || rho == 64; }
+bool diffuse_tb_supported(int rho) { return rho == 16 || rho == 32 || rho == 64; }
 
 hipError_t launch_diffuse_tb(const PassArgs &a, int T, const float *in, float *out,
                              float alpha) {
   if (T < 1 || T > kMaxDiffuseStepsPerPass) return hipErrorInvalidValue;
   switch (a.rho) {
+    case 16: return diffuse_tb_rho<16>(a, T, in, out, alpha);
     case 32: return diffuse_tb_rho<32>(a, T, in, out, alpha);
     case 64: return diffuse_tb_rho<64>(a, T, in, out, alpha);
     default: return hipErrorInvalidValue;

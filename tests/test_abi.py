@@ -225,6 +225,7 @@ def test_diffuse_steps_validation(lib):
     r = 8
     assert lib.sg_diffuse_steps(0, r, 64, 10, 9, a, b, w, 0.2, None) == sg.SG_EINVAL
     assert lib.sg_diffuse_steps(0, r, 128, 10, 4, a, b, w, 0.2, None) == sg.SG_EINVAL
+    assert lib.sg_diffuse_steps(0, r, 8, 10, 4, a, b, w, 0.2, None) == sg.SG_EINVAL
     assert lib.sg_diffuse_steps(0, r, 64, -2, 4, a, b, w, 0.2, None) == sg.SG_EINVAL
     assert lib.sg_diffuse_steps(0, r, 64, 10, 4, a, b, None, 0.2, None) == sg.SG_EINVAL
     assert lib.sg_diffuse_steps(0, r, 64, 10, 4, a, ctypes.c_void_p(0x100000 + 4096), w, 0.2, None) == sg.SG_EALIAS

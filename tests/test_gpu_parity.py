@@ -333,7 +333,7 @@ def test_diffusion_full_size_sampled(rho):
 # ------------------------------------------------------------------ multi-step diffusion
 
 @pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
-@pytest.mark.parametrize("rho", [32, 64])
+@pytest.mark.parametrize("rho", [16, 32, 64])
 @pytest.mark.parametrize("r,steps,spp", [(6, 1, 8), (6, 8, 8), (7, 13, 8), (8, 30, 5), (9, 17, 3),
                                          (10, 40, 8), (10, 0, 8), (8, 9, 1), (5, 11, 8)])
 def test_diffuse_steps_equal_one_step_calls_and_oracle(map_kind, rho, r, steps, spp):
@@ -352,7 +352,8 @@ def test_diffuse_steps_equal_one_step_calls_and_oracle(map_kind, rho, r, steps, 
     assert max_abs <= DIFF_RTOL * scale and rel_l2 <= DIFF_RTOL
 
 
-@pytest.mark.parametrize("map_kind,rho", [("lambda", 32), ("bbox", 32), ("lambda", 64)])
+@pytest.mark.parametrize("map_kind,rho", [("lambda", 16), ("lambda", 32), ("bbox", 32),
+                                          ("lambda", 64)])
 def test_diffuse_steps_full_size_all_cells(map_kind, rho):
     # every cell of the r = 14 field after two 8-step passes (the benchmark's
     # launch configuration) against the FP64 oracle, at the stated tolerance
@@ -371,7 +372,7 @@ def test_diffuse_steps_full_size_all_cells(map_kind, rho):
     assert max_abs <= DIFF_RTOL * scale and rel_l2 <= DIFF_RTOL
 
 
-@pytest.mark.parametrize("rho", [32, 64])
+@pytest.mark.parametrize("rho", [16, 32, 64])
 def test_diffuse_steps_full_size_sampled(rho):
     r, steps = 14, 500
     note(f"diffuse_steps full-size r={r} rho={rho} {steps} steps, 8 per pass")
