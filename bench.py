@@ -29,6 +29,7 @@ CA_BYTES_PER_CELL = 2          # read own state once, write it once
 WRITE_BYTES_PER_CELL = 1       # store the constant once
 RHOS = (4, 8, 16, 32, 64, 128, 256)
 TB_RHOS = (64, 128, 256)
+TB_SMALL_RHOS = (16, 32)        # byte-plane tile passes, up to 16 generations per pass
 R = 16
 SEED = 1706
 PAPER_BEST_VS_BEST = "about 10x (best lambda, rho=16, vs best bounding box, rho=32; Titan-X Pascal GP102; write pass at n=2^16)"
@@ -463,14 +464,16 @@ def main():
     Out = torch.zeros_like(A)
     Work = torch.zeros_like(A)
     for map_kind in ("lambda", "bbox"):
-        for rho in [x for x in args.rho if x in TB_RHOS]:
-            for T in args.per_pass:
-                def run():
-                    sg.sg_ca_steps(map_kind, R, rho, args.steps, A, Out, Work, steps_per_pass=T)
-                ms = time_region(torch, run, 1, 1 if args.warmup else 0) / args.steps
-                multi[map_kind][(rho, T)] = ms
-                log(f"ca {T:2d}/pass   {map_kind:6s} rho={rho:3d}: {ms * 1e3:9.2f} us/step  "
-                    f"{cells / (ms * 1e-3) / 1e9:8.2f} Gcells/s")
+        shapes = [(rho, T) for rho in args.rho if rho in TB_RHOS for T in args.per_pass]
+        shapes += [(rho, T) for rho in args.rho if rho in TB_SMALL_RHOS
+                   for T in args.per_pass if T <= 16]
+        for rho, T in shapes:
+            def run():
+                sg.sg_ca_steps(map_kind, R, rho, args.steps, A, Out, Work, steps_per_pass=T)
+            ms = time_region(torch, run, 1, 1 if args.warmup else 0) / args.steps
+            multi[map_kind][(rho, T)] = ms
+            log(f"ca {T:2d}/pass   {map_kind:6s} rho={rho:3d}: {ms * 1e3:9.2f} us/step  "
+                f"{cells / (ms * 1e-3) / 1e9:8.2f} Gcells/s")
     del Out, Work
 
     # block-compacted storage: only the fractal tiles, (4/3)^k * 3^r bytes

@@ -165,8 +165,11 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
   if (st != SG_OK) return st;
   if (steps < 0 || steps_per_pass < 0 || steps_per_pass > sg::kMaxStepsPerPass) return SG_EINVAL;
   const bool tb_ok = sg::life_tb_supported(rho);
-  if (steps_per_pass == 0) steps_per_pass = tb_ok ? sg::kDefaultStepsPerPass : 1;
-  if (steps_per_pass > 1 && !tb_ok) return SG_EINVAL;
+  const bool tbs_ok = sg::life_tbs_supported(rho);  // small tiles: up to 16 per pass
+  if (steps_per_pass == 0)
+    steps_per_pass = tb_ok ? sg::kDefaultStepsPerPass : (tbs_ok ? sg::kMaxSmallTileSteps : 1);
+  if (steps_per_pass > 1 && !tb_ok && !(tbs_ok && steps_per_pass <= sg::kMaxSmallTileSteps))
+    return SG_EINVAL;
   if (!d_in || !d_out || misaligned(d_in) || misaligned(d_out)) return SG_EINVAL;
   const size_t bytes = ((size_t)1 << r) * ((size_t)1 << r);
   if (overlaps(d_in, d_out, bytes)) return SG_EALIAS;
@@ -184,7 +187,8 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
     uint8_t *dst = ((passes - k) % 2 == 0) ? d_out : d_work;
     const int T = k < passes ? steps_per_pass : steps - (passes - 1) * steps_per_pass;
     const hipError_t e = T == 1 && steps_per_pass == 1 ? sg::launch_life(a, src, dst)
-                                                       : sg::launch_life_tb(a, T, src, dst);
+                         : tb_ok                          ? sg::launch_life_tb(a, T, src, dst)
+                                                          : sg::launch_life_tbs(a, T, src, dst);
     if (e != hipSuccess) return hip_status(e);
     src = dst;
   }

@@ -40,6 +40,11 @@ constexpr int kMaxStepsPerPass = 32;
 constexpr int kDefaultStepsPerPass = 32;  // what steps_per_pass = 0 selects
 bool life_tb_supported(int rho);
 hipError_t launch_life_tb(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
+// The same for tiles of side 16 or 32 (byte planes, one 16-cell chunk of
+// halo): T in [1, kMaxSmallTileSteps].
+constexpr int kMaxSmallTileSteps = 16;
+bool life_tbs_supported(int rho);
+hipError_t launch_life_tbs(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
 
 // Block-compacted storage (tiles of side rho in {64, 128, 256}, lambda order).
 hipError_t launch_map_lambda_inverse(int rb, int32_t *d_out, hipStream_t s);

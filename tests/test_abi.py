@@ -139,8 +139,12 @@ def test_ca_steps_validation(lib):
     # steps_per_pass out of range, or > 1 where the tile side has no temporal blocking
     assert lib.sg_ca_steps(0, r, 64, 10, 33, a, b, w, None) == sg.SG_EINVAL
     assert lib.sg_ca_steps(0, r, 64, 10, -1, a, b, w, None) == sg.SG_EINVAL
-    assert lib.sg_ca_steps(0, r, 16, 10, 4, a, b, w, None) == sg.SG_EINVAL
-    assert lib.sg_ca_steps(0, r, 32, 10, 2, a, b, w, None) == sg.SG_EINVAL
+    # small tiles (16, 32) take up to 16 generations per pass; 8 and below none
+    assert lib.sg_ca_steps(0, r, 16, 10, 17, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 32, 10, 32, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 8, 10, 2, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 4, 10, 4, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 16, 17, 16, a, b, None, None) == sg.SG_EINVAL  # needs work
     assert lib.sg_ca_steps(0, r, 64, -1, 4, a, b, w, None) == sg.SG_EINVAL
     # more than one pass needs a work buffer, distinct from in and out
     assert lib.sg_ca_steps(0, r, 64, 17, 16, a, b, None, None) == sg.SG_EINVAL

@@ -236,7 +236,11 @@ def gpu_ca_steps(map_kind, r, rho, a0, steps, spp):
     (9, 64, 33, 16), (10, 128, 50, 16), (10, 256, 17, 16), (10, 64, 12, 1), (11, 128, 31, 7),
     (8, 16, 9, 1), (9, 4, 3, 0), (10, 256, 0, 16), (12, 256, 100, 16), (12, 128, 100, 11),
     (7, 64, 17, 17), (8, 64, 40, 32), (9, 128, 70, 24), (10, 256, 33, 32), (12, 256, 100, 32),
-    (11, 64, 64, 32)])
+    (11, 64, 64, 32),
+    # small tiles, up to 16 generations per pass (0: the library's choice, 16)
+    (4, 16, 5, 16), (5, 16, 9, 4), (5, 32, 20, 16), (6, 16, 17, 16), (7, 32, 23, 8),
+    (8, 32, 40, 16), (9, 16, 33, 16), (10, 32, 50, 16), (10, 16, 7, 3), (11, 32, 31, 7),
+    (12, 32, 100, 16), (12, 16, 100, 0), (8, 16, 1, 2), (9, 32, 16, 16)])
 def test_ca_steps_exact(map_kind, r, rho, steps, spp):
     note(f"ca_steps {map_kind} r={r} rho={rho} steps={steps} per_pass={spp}")
     a0 = inputs.bernoulli_state(r, 0.5, 1706 + 3 * r)
@@ -258,13 +262,15 @@ def life_r16_36():
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("map_kind,rho", [("lambda", 256), ("bbox", 256), ("lambda", 128)])
-def test_ca_steps_full_size_exact(life_r16_36, map_kind, rho):
-    # every cell of the r = 16 state after one 32-generation pass and one
-    # 4-generation pass: the benchmark's launch configuration
+@pytest.mark.parametrize("map_kind,rho,spp", [("lambda", 256, 32), ("bbox", 256, 32),
+                                              ("lambda", 128, 32), ("lambda", 32, 16),
+                                              ("bbox", 32, 16), ("lambda", 16, 16)])
+def test_ca_steps_full_size_exact(life_r16_36, map_kind, rho, spp):
+    # every cell of the r = 16 state after 36 generations in the benchmark's
+    # launch configurations (32 + 4 per pass; small tiles 16 + 16 + 4)
     a0, ref = life_r16_36
-    note(f"ca_steps full size exact {map_kind} r=16 rho={rho} 36 steps, 32 per pass")
-    got = gpu_ca_steps(map_kind, 16, rho, a0, 36, 32)
+    note(f"ca_steps full size exact {map_kind} r=16 rho={rho} 36 steps, {spp} per pass")
+    got = gpu_ca_steps(map_kind, 16, rho, a0, 36, spp)
     assert torch.equal(got, ref)
     del got
 
