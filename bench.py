@@ -28,8 +28,9 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 CA_BYTES_PER_CELL = 2          # read own state once, write it once
 WRITE_BYTES_PER_CELL = 1       # store the constant once
 RHOS = (4, 8, 16, 32, 64, 128, 256)
-TB_RHOS = (64, 128, 256)
-TB_SMALL_RHOS = (16, 32)        # byte-plane tile passes, up to 16 generations per pass
+TB_RHOS = (32, 64, 128, 256)
+TB_SMALL_RHOS = (16,)           # byte-plane tile pass, up to 16 generations per pass
+COMPACT_RHOS = (64, 128, 256)   # tile sides of block-compacted storage
 R = 16
 SEED = 1706
 PAPER_BEST_VS_BEST = "about 10x (best lambda, rho=16, vs best bounding box, rho=32; Titan-X Pascal GP102; write pass at n=2^16)"
@@ -478,7 +479,7 @@ def main():
 
     # block-compacted storage: only the fractal tiles, (4/3)^k * 3^r bytes
     compact = {}
-    for rho in [x for x in args.rho if x in TB_RHOS]:
+    for rho in [x for x in args.rho if x in COMPACT_RHOS]:
         size = sg.sg_compact_bytes(R, rho)
         Cin = torch.empty(size, dtype=torch.uint8, device=dev)
         sg.sg_compact_pack(R, rho, A, Cin)

@@ -143,8 +143,8 @@ SG_API int sg_ca_step(int map, int r, int rho, const uint8_t *d_in,
  * (temporal blocking), so HBM traffic per generation falls by that factor.
  * The result is identical to `steps` calls of sg_ca_step.
  *   steps_per_pass: 1 (one launch per generation, any rho), 2..32 (rho in
- *     {64, 128, 256}), 2..16 (rho in {16, 32}), or 0 for the library's
- *     choice (the largest where supported, else 1).
+ *     {32, 64, 128, 256}), 2..16 (rho = 16), or 0 for the library's choice
+ *     (the largest where supported, else 1).
  *   d_in: read only.  d_out: receives the state after `steps` generations.
  *   d_work: a third n * n buffer used when more than one pass runs (may be
  *     NULL otherwise).  All three: device, 16-byte aligned, pairwise

@@ -164,8 +164,8 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
   const int st = pass_args(map, r, rho, stream, a);
   if (st != SG_OK) return st;
   if (steps < 0 || steps_per_pass < 0 || steps_per_pass > sg::kMaxStepsPerPass) return SG_EINVAL;
-  const bool tb_ok = sg::life_tb_supported(rho);
-  const bool tbs_ok = sg::life_tbs_supported(rho);  // small tiles: up to 16 per pass
+  const bool tb_ok = sg::life_tb_dense_supported(rho);
+  const bool tbs_ok = sg::life_tbs_supported(rho);  // side 16: up to 16 per pass
   if (steps_per_pass == 0)
     steps_per_pass = tb_ok ? sg::kDefaultStepsPerPass : (tbs_ok ? sg::kMaxSmallTileSteps : 1);
   if (steps_per_pass > 1 && !tb_ok && !(tbs_ok && steps_per_pass <= sg::kMaxSmallTileSteps))

@@ -38,10 +38,13 @@ hipError_t launch_diffuse(const PassArgs &a, const float *in, float *out, float 
 // for tile sides rho in {64, 128, 256}.
 constexpr int kMaxStepsPerPass = 32;
 constexpr int kDefaultStepsPerPass = 32;  // what steps_per_pass = 0 selects
+// Tile sides of the compact, batched and served paths (64, 128, 256), and of
+// the dense pass (those and 32).
 bool life_tb_supported(int rho);
+bool life_tb_dense_supported(int rho);
 hipError_t launch_life_tb(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
-// The same for tiles of side 16 or 32 (byte planes, one 16-cell chunk of
-// halo): T in [1, kMaxSmallTileSteps].
+// The same for tiles of side 16 (byte planes, one 16-cell chunk of halo):
+// T in [1, kMaxSmallTileSteps].
 constexpr int kMaxSmallTileSteps = 16;
 bool life_tbs_supported(int rho);
 hipError_t launch_life_tbs(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);

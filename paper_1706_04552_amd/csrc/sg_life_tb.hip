@@ -195,7 +195,8 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   constexpr int CH = 2 * W;           // 16-byte chunks per region row
   constexpr int L = kSegRows;
   static_assert(L <= 8, "row bits of a segment are kept in 8 bits");
-  static_assert(RHO % 64 == 0, "tiles span whole 64-byte granules");
+  static_assert(RHO % 32 == 0, "tile rows are whole 32-cell words");
+  constexpr int G = RHO >= 64 ? 64 : RHO;  // store granule: 64 bytes, or the whole row
   const int R = RHO + 2 * T;          // region rows
   const int NB = (R + L - 1) / L;     // segment blocks per word column
   const int RP = NB * L;              // region rows rounded up to whole blocks
@@ -319,14 +320,14 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   }
   const uint16_t *fin = reinterpret_cast<const uint16_t *>((T & 1) ? plane1 : plane0);
 
-  // 4. unpack and store the tile, whole 64-byte granules
+  // 4. unpack and store the tile, whole granules (64 bytes, or a 32-byte row)
   constexpr int TC = RHO / 16;
   for (int e = tid; e < RHO * TC; e += kTbThreads) {
     const int ty = e / TC, j = e - (e / TC) * TC;
     const int y = Y0 + ty, x = X0 + 16 * j;
     // the embedding keeps granules without a gasket cell untouched; a compact
     // tile is rewritten whole
-    if (!Mem::kCompact && ((x & ~63) & y) != 0) continue;
+    if (!Mem::kCompact && ((x & ~(G - 1)) & y) != 0) continue;
     const int w = 1 + (j >> 1), half = j & 1;  // region chunk j + 2
     const uint32_t bits = fin[((T + ty + 1) * PW + (w + 1)) * 2 + half];
     *reinterpret_cast<uint4 *>(mem.dst(y, x)) = unpack16(bits);
@@ -406,7 +407,9 @@ __global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restric
 
 template <int RHO>
 size_t tb_lds_bytes(int T) {
-  const int W = RHO / 32 + 1, PW = plane_pitch(W), R = RHO + 2 * T;
+  // the layout of tb_tile: two planes, the row patterns, and a segment list
+  // of up to W * NB entries (W = the tile's words plus a halo word each side)
+  const int W = RHO / 32 + 2, PW = plane_pitch(W), R = RHO + 2 * T;
   const int NB = (R + kSegRows - 1) / kSegRows, RP = NB * kSegRows, PR = RP + 2;
   return sizeof(uint32_t) * (size_t)(2 * PR * PW + RP + W * NB);
 }
@@ -485,10 +488,12 @@ hipError_t launch_life_tb_compact(const PassArgs &a, int T, const uint8_t *in, u
 }
 
 bool life_tb_supported(int rho) { return rho == 64 || rho == 128 || rho == 256; }
+bool life_tb_dense_supported(int rho) { return rho == 32 || life_tb_supported(rho); }
 
 hipError_t launch_life_tb(const PassArgs &a, int T, const uint8_t *in, uint8_t *out) {
   if (T < 1 || T > kMaxStepsPerPass) return hipErrorInvalidValue;
   switch (a.rho) {
+    case 32: return life_tb_rho<32>(a, T, in, out);
     case 64: return life_tb_rho<64>(a, T, in, out);
     case 128: return life_tb_rho<128>(a, T, in, out);
     case 256: return life_tb_rho<256>(a, T, in, out);

@@ -1,5 +1,6 @@
-// Temporally blocked B3/S23 life for small tiles (rho in {16, 32}) on the
-// gasket (gfx950), the block sides below the 64-cell words of k_life_tb.
+// Temporally blocked B3/S23 life for tiles of side 16 on the gasket (gfx950),
+// below the 32-cell words of k_life_tb.  Written for any side that is a
+// multiple of 16; side 32 is served by k_life_tb, which is faster there.
 //
 // One workgroup owns one rho x rho tile of the map and advances it by T <= 16
 // generations per pass:
@@ -270,13 +271,12 @@ hipError_t life_tbs_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *ou
 
 }  // namespace
 
-bool life_tbs_supported(int rho) { return rho == 16 || rho == 32; }
+bool life_tbs_supported(int rho) { return rho == 16; }
 
 hipError_t launch_life_tbs(const PassArgs &a, int T, const uint8_t *in, uint8_t *out) {
   if (T < 1 || T > kMaxSmallTileSteps) return hipErrorInvalidValue;
   switch (a.rho) {
     case 16: return life_tbs_rho<16>(a, T, in, out);
-    case 32: return life_tbs_rho<32>(a, T, in, out);
     default: return hipErrorInvalidValue;
   }
 }

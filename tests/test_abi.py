@@ -139,9 +139,9 @@ def test_ca_steps_validation(lib):
     # steps_per_pass out of range, or > 1 where the tile side has no temporal blocking
     assert lib.sg_ca_steps(0, r, 64, 10, 33, a, b, w, None) == sg.SG_EINVAL
     assert lib.sg_ca_steps(0, r, 64, 10, -1, a, b, w, None) == sg.SG_EINVAL
-    # small tiles (16, 32) take up to 16 generations per pass; 8 and below none
+    # side 16 takes up to 16 generations per pass, side 32 up to 32; 8 and below none
     assert lib.sg_ca_steps(0, r, 16, 10, 17, a, b, w, None) == sg.SG_EINVAL
-    assert lib.sg_ca_steps(0, r, 32, 10, 32, a, b, w, None) == sg.SG_EINVAL
+    assert lib.sg_ca_steps(0, r, 32, 10, 33, a, b, w, None) == sg.SG_EINVAL
     assert lib.sg_ca_steps(0, r, 8, 10, 2, a, b, w, None) == sg.SG_EINVAL
     assert lib.sg_ca_steps(0, r, 4, 10, 4, a, b, w, None) == sg.SG_EINVAL
     assert lib.sg_ca_steps(0, r, 16, 17, 16, a, b, None, None) == sg.SG_EINVAL  # needs work

@@ -240,7 +240,8 @@ def gpu_ca_steps(map_kind, r, rho, a0, steps, spp):
     # small tiles, up to 16 generations per pass (0: the library's choice, 16)
     (4, 16, 5, 16), (5, 16, 9, 4), (5, 32, 20, 16), (6, 16, 17, 16), (7, 32, 23, 8),
     (8, 32, 40, 16), (9, 16, 33, 16), (10, 32, 50, 16), (10, 16, 7, 3), (11, 32, 31, 7),
-    (12, 32, 100, 16), (12, 16, 100, 0), (8, 16, 1, 2), (9, 32, 16, 16)])
+    (12, 32, 100, 16), (12, 16, 100, 0), (8, 16, 1, 2), (9, 32, 16, 16),
+    (10, 32, 64, 32), (12, 32, 100, 0), (7, 32, 33, 24)])
 def test_ca_steps_exact(map_kind, r, rho, steps, spp):
     note(f"ca_steps {map_kind} r={r} rho={rho} steps={steps} per_pass={spp}")
     a0 = inputs.bernoulli_state(r, 0.5, 1706 + 3 * r)
@@ -263,11 +264,11 @@ def life_r16_36():
 
 
 @pytest.mark.parametrize("map_kind,rho,spp", [("lambda", 256, 32), ("bbox", 256, 32),
-                                              ("lambda", 128, 32), ("lambda", 32, 16),
-                                              ("bbox", 32, 16), ("lambda", 16, 16)])
+                                              ("lambda", 128, 32), ("lambda", 32, 32),
+                                              ("bbox", 32, 32), ("lambda", 16, 16)])
 def test_ca_steps_full_size_exact(life_r16_36, map_kind, rho, spp):
     # every cell of the r = 16 state after 36 generations in the benchmark's
-    # launch configurations (32 + 4 per pass; small tiles 16 + 16 + 4)
+    # launch configurations (32 + 4 per pass; side 16: 16 + 16 + 4)
     a0, ref = life_r16_36
     note(f"ca_steps full size exact {map_kind} r=16 rho={rho} 36 steps, {spp} per pass")
     got = gpu_ca_steps(map_kind, 16, rho, a0, 36, spp)
