@@ -4,24 +4,24 @@
 // advances it by T <= 8 explicit diffusion steps per pass:
 //  1. load the tile plus a halo of T rows above/below and 8 cells left/right
 //     (two float4 chunks) into registers, every load issued before the first
-//     wait, skipping chunks with no gasket cell;
-//  2. write the first plane, and list the 4-cell chunks that hold a gasket
-//     cell and can reach the tile in T steps (wavefront ballot + prefix
-//     count), each as one word: its region index and its distance to the
-//     tile.  The list is built in the second plane's memory, which is not in
-//     use yet;
-//  3. each thread takes its listed chunks into registers: the chunk's LDS
+//     wait, skipping chunks with no gasket cell; while the loads are in
+//     flight, list the 4-cell chunks that hold a gasket cell and can reach
+//     the tile in T steps (wavefront ballot + prefix count), each as one
+//     word: its region index and its distance to the tile.  The list is
+//     built in the second plane's memory, which is not in use yet; then
+//     write the first plane;
+//  2. each thread takes its listed chunks into registers: the chunk's LDS
 //     offset, the number of steps in which it can still reach the tile, and
-//     per cell -deg (its count of in-grid gasket neighbours) and a weight
+//     per cell its count deg of in-grid gasket neighbours and a weight
 //     (alpha on the gasket, 0 off it);
-//  4. clear the second plane, then T times: every
+//  3. clear the second plane, then T times: every
 //     held chunk updates its 4 cells with the arithmetic of diffuse_cell, the
 //     function the one-step kernels use, as
 //     fma(w, fma(-deg, u, (W + E) + (N + S)), u); off the gasket w = 0 keeps
-//     the value, which is 0.  A chunk's own values stay in registers; the
+//     the value, which is 0 (the inner fma is finite there).  A chunk's own values stay in registers; the
 //     neighbours come from the other plane, and the planes ping-pong with a
 //     barrier between steps;
-//  5. store the tile, every 64-byte granule that holds a gasket cell in full.
+//  4. store the tile, every 64-byte granule that holds a gasket cell in full.
 //
 // The 4-neighbour stencil moves information one cell per step.  Cells outside
 // the region hold wrong values (the plane has no cells there: a row's west
@@ -60,16 +60,13 @@ size_t dt_lds_bytes(int T) {
 constexpr int kChunkBits = 11;
 constexpr int kDistShift = 27;
 
-// Gasket cells of the 4-cell chunk at column x (a multiple of 4) of row y, as
-// a 4-bit mask (bit j: cell x + j): cell x + j is on the gasket iff x & y == 0
-// and j & (y mod 4) == 0.  Rows outside the grid hold no cell.
-__device__ __forceinline__ uint32_t chunk_row_mask(int x, int y, int n) {
-  return (y >= 0 && y < n && (x & y) == 0) ? (0x135Fu >> (4 * (y & 3))) & 0xfu : 0u;
-}
-
-// Bit j of a 4-bit mask moved to bit 3j (the low bit of cell j's count field).
-__device__ __forceinline__ uint32_t spread_nibble(uint32_t m) {
-  return (m & 1u) | ((m & 2u) << 2) | ((m & 4u) << 4) | ((m & 8u) << 6);
+// Gasket cells of a 4-cell chunk whose first cell (column x, a multiple of 4)
+// is on the gasket in row y, one byte per cell (byte j = 1 iff cell x + j is
+// on the gasket): x + j and y share no bit iff x & y == 0 and j & (y mod 4)
+// == 0.  `ymod4` is y mod 4.
+__device__ __forceinline__ uint32_t chunk_row_bytes(uint32_t ymod4) {
+  const uint32_t nib = (0x135Fu >> (4u * ymod4)) & 0xFu;  // bit j: j & ymod4 == 0
+  return (nib * 0x00204081u) & 0x01010101u;              // bit j -> byte j
 }
 
 // Distance (in steps of the 4-neighbour stencil) from region chunk (i, c) to
@@ -115,17 +112,31 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
   float *plane0 = flds;
   float *plane1 = flds + R * G::CW;
 
-  // 1. load
+  if (tid == 0) nchunk = 0u;
+  __syncthreads();  // the count is zero before any wave adds to it
+
+  // 1. load, and list the chunks while the loads are in flight (the list is
+  //    built in plane1's memory)
+  const uint64_t lanes_below = (1ull << lane) - 1ull;
+  uint32_t *list = reinterpret_cast<uint32_t *>(plane1);
   float4 v[KS];
-  bool has[KS];
 #pragma unroll
   for (int kk = 0; kk < KS; ++kk) {
     const int e = tid + kk * NT;
     const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
     const int y = yr0 + i, x = xr0 + 4 * c;
-    has[kk] = e < nslots && y >= 0 && y < n && x >= 0 && x < n && (x & y) == 0;
-    v[kk] = has[kk] ? *reinterpret_cast<const float4 *>(in + (size_t)y * n + x)
-                    : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const bool has = e < nslots && y >= 0 && y < n && x >= 0 && x < n && (x & y) == 0;
+    v[kk] = has ? *reinterpret_cast<const float4 *>(in + (size_t)y * n + x)
+                : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const int d = chunk_distance<RHO>(i, c, T);
+    const bool live = has && d < T;
+    const uint64_t ball = __ballot(live);
+    if (ball != 0ull) {  // uniform: every lane of the wave is here
+      uint32_t base = 0u;
+      if (lane == 0) base = atomicAdd(&nchunk, (uint32_t)__popcll(ball));
+      base = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);
+      if (live) list[base + (uint32_t)__popcll(ball & lanes_below)] = (uint32_t)e | ((uint32_t)d << kDistShift);
+    }
   }
   // plane0 takes the loaded values (chunk e starts at float 4e, since rows are
   // CW = 4 CC floats)
@@ -136,67 +147,45 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
     const int e = tid + kk * NT;
     if (e < nslots) q0[e] = v[kk];
   }
-  if (tid == 0) nchunk = 0u;
-  __syncthreads();
-
-  // 2. the list, built in plane1's memory
-  uint32_t *list = reinterpret_cast<uint32_t *>(plane1);
-#pragma unroll
-  for (int kk = 0; kk < KS; ++kk) {
-    const int e = tid + kk * NT;
-    const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
-    const int d = chunk_distance<RHO>(i, c, T);
-    const bool live = has[kk] && d < T;
-    const uint32_t word = (uint32_t)e | ((uint32_t)d << kDistShift);
-    const uint64_t ball = __ballot(live);
-    const uint32_t before = (uint32_t)__popcll(ball & ((1ull << lane) - 1ull));
-    uint32_t base = 0u;
-    if (lane == 0 && ball != 0ull) base = atomicAdd(&nchunk, (uint32_t)__popcll(ball));
-    base = __shfl(base, 0);
-    if (live) list[base + before] = word;
-  }
   __syncthreads();
   const int nc = (int)nchunk;
   const int kheld = (nc + NT - 1) / NT;  // register slots in use (uniform)
 
-  // 3. this thread's chunks, in registers
+  // 2. this thread's chunks, in registers
   int off[KS], steps_live[KS];
-  float nd[KS][4], wt[KS][4];
+  float deg[KS][4], wt[KS][4];
 #pragma unroll
   for (int kk = 0; kk < KS; ++kk) {
     const int k = tid + kk * NT;
     off[kk] = 0;
     steps_live[kk] = 0;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) nd[kk][j] = wt[kk][j] = 0.0f;
+    for (int j = 0; j < 4; ++j) deg[kk][j] = wt[kk][j] = 0.0f;
     if (kk < kheld && k < nc) {
       const uint32_t word = list[k];
       const int e = (int)(word & ((1u << kChunkBits) - 1u));
       off[kk] = 4 * e;  // rows are CW = 4 CC floats, so chunk e starts at float 4e
       steps_live[kk] = T - (int)(word >> kDistShift);
-      // 4-bit masks of the gasket cells of the chunk's row and the rows above
-      // and below give each cell's neighbour count, summed in 3-bit fields
+      // neighbour counts, one byte per cell: north + south + west + east,
+      // each 0 or 1 (a listed chunk's first cell is on the gasket)
       const int i = e / G::CC, c = e - (e / G::CC) * G::CC;
       const int y = yr0 + i, x = xr0 + 4 * c;
-      const uint32_t S = chunk_row_mask(x, y, n), U = chunk_row_mask(x, y - 1, n),
-                     D = chunk_row_mask(x, y + 1, n);
-      const uint32_t lb = (x > 0 && ((x - 1) & y) == 0) ? 1u : 0u;
-      const uint32_t rbit = (x + 4 < n && ((x + 4) & y) == 0) ? 1u : 0u;
-      const uint32_t L = ((S << 1) | lb) & 0xfu, Rm = (S >> 1) | (rbit << 3);
-      const uint32_t degs =
-          spread_nibble(U) + spread_nibble(D) + spread_nibble(L) + spread_nibble(Rm);
+      const uint32_t S = chunk_row_bytes((uint32_t)y & 3u);
+      const uint32_t U = (y > 0 && (x & (y - 1)) == 0) ? chunk_row_bytes((uint32_t)(y - 1) & 3u) : 0u;
+      const uint32_t D = (y + 1 < n && (x & (y + 1)) == 0) ? chunk_row_bytes((uint32_t)(y + 1) & 3u) : 0u;
+      const uint32_t wb = (x > 0 && ((x - 1) & y) == 0) ? 1u : 0u;
+      const uint32_t eb = (x + 4 < n && ((x + 4) & y) == 0) ? 0x01000000u : 0u;
+      const uint32_t degs = U + D + ((S << 8) | wb) + ((S >> 8) | eb);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const bool self = (S >> j) & 1u;
-        const float deg = (float)((degs >> (3 * j)) & 7u);
-        nd[kk][j] = self ? -deg : 0.0f;
-        wt[kk][j] = self ? alpha : 0.0f;
+        deg[kk][j] = (float)((degs >> (8 * j)) & 0xFFu);  // one v_cvt_f32_ubyte<j>
+        wt[kk][j] = ((S >> (8 * j)) & 1u) ? alpha : 0.0f;
       }
     }
   }
   __syncthreads();  // the list is read before plane1 is cleared
 
-  // 4. plane1 cleared, then T steps
+  // 3. plane1 cleared, then T steps
   for (int e = tid; e < nslots; e += NT) q1[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   __syncthreads();
   float4 cur[KS];
@@ -223,7 +212,7 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
         const float w = j == 0 ? Wn : cu[j - 1];
         const float ee = j == 3 ? En : cu[j + 1];
         o[j] = __builtin_fmaf(wt[kk][j],
-                              __builtin_fmaf(nd[kk][j], cu[j], (w + ee) + (nu[j] + su[j])), cu[j]);
+                              __builtin_fmaf(-deg[kk][j], cu[j], (w + ee) + (nu[j] + su[j])), cu[j]);
       }
       cur[kk] = make_float4(o[0], o[1], o[2], o[3]);
       *reinterpret_cast<float4 *>(dst + off[kk]) = cur[kk];
@@ -232,7 +221,7 @@ __global__ __launch_bounds__(DtGeom<RHO>::NT) void k_diffuse_tb(const float *__r
   }
   const float *fin = (T & 1) ? plane1 : plane0;
 
-  // 5. store the tile, whole 64-byte granules (16 floats)
+  // 4. store the tile, whole 64-byte granules (16 floats)
   constexpr int TC = RHO / 4;
   for (int e = tid; e < RHO * TC; e += NT) {
     const int ty = e / TC, c = e - (e / TC) * TC;
