@@ -62,6 +62,17 @@ constexpr int plane_pitch(int W) {
 
 constexpr int rho_log2_const(int rho) { return rho <= 1 ? 0 : 1 + rho_log2_const(rho / 2); }
 
+// e / d for d >= 4 and e (d - 1) < 2^20, given m = ceil(2^20 / d): e * m then
+// fits 32 bits (and 24-bit operands), and e * m / 2^20 exceeds e / d by at
+// most e (d - 1) / (d 2^20) < 1 / d, which never carries it past the next
+// integer.
+__host__ __device__ constexpr uint32_t div_small_magic(uint32_t d) {
+  return ((1u << 20) + d - 1u) / d;
+}
+__device__ __forceinline__ int div_small(int e, uint32_t m) {
+  return (int)(__umul24((uint32_t)e, m) >> 20);
+}
+
 // 16 bytes holding 0/1 -> 16 bits (bit i = byte i).
 __device__ __forceinline__ uint32_t pack16(const uint4 v) {
   auto p4 = [](uint32_t w) { return (w | (w >> 7) | (w >> 14) | (w >> 21)) & 0xFu; };
@@ -134,17 +145,19 @@ __device__ __forceinline__ uint32_t life_rule(const RowSums &u, const RowSums &m
 
 // Where a tile pass reads and writes cells.
 //
-// DenseMem: the n x n embedding itself.
+// DenseMem: the 2^lgn x 2^lgn embedding itself (row y at y << lgn; callers
+// pass cells inside the grid).
 struct DenseMem {
   const uint8_t *in;
   uint8_t *out;
-  int n;
+  int lgn;
   static constexpr bool kCompact = false;
   __device__ __forceinline__ void prepare(int, uint32_t, uint32_t, int) const {}
-  __device__ __forceinline__ const uint8_t *src(int y, int x) const {
-    return in + (size_t)y * n + x;
+  __device__ __forceinline__ size_t off(int y, int x) const {
+    return ((size_t)(uint32_t)y << lgn) + (uint32_t)x;
   }
-  __device__ __forceinline__ uint8_t *dst(int y, int x) const { return out + (size_t)y * n + x; }
+  __device__ __forceinline__ const uint8_t *src(int y, int x) const { return in + off(y, x); }
+  __device__ __forceinline__ uint8_t *dst(int y, int x) const { return out + off(y, x); }
 };
 
 // CompactMem: only the fractal rho x rho tiles, tile omega stored contiguously
@@ -196,6 +209,9 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   constexpr int L = kSegRows;
   static_assert(L <= 8, "row bits of a segment are kept in 8 bits");
   static_assert(RHO % 32 == 0, "tile rows are whole 32-cell words");
+  constexpr int NBMAX = (RHO + 2 * kMaxStepsPerPass + L - 1) / L;
+  static_assert((RHO + 2 + L - 1) / L >= 4 && W * NBMAX * (NBMAX - 1) < (1 << 20),
+                "div_small covers the segment list's e / NB");
   constexpr int G = RHO >= 64 ? 64 : RHO;  // store granule: 64 bytes, or the whole row
   const int R = RHO + 2 * T;          // region rows
   const int NB = (R + L - 1) / L;     // segment blocks per word column
@@ -225,28 +241,33 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   if (tid == 0) nseg = 0u;
   __syncthreads();
 
-  // 1. load and bit-pack the region, kLoadBatch loads in flight per thread
+  // 1. load and bit-pack the region, kLoadBatch loads in flight per thread.
+  //    Thread tid takes chunk column jlo + tid % CHL of region rows tid / CHL,
+  //    tid / CHL + RPB, ... (RPB = kTbThreads / CHL rows per round), so the
+  //    column's part of every address is found once.
   uint16_t *p0h = reinterpret_cast<uint16_t *>(plane0);
-  for (int e0 = 0; e0 < R * CHL; e0 += kTbThreads * kLoadBatch) {
-    uint4 v[kLoadBatch];
-    int slot[kLoadBatch];
+  {
+    const int RPB = kTbThreads / CHL;
+    const int ti = tid / CHL, j = jlo + (tid - ti * CHL);
+    const int x = X0 - 32 + 16 * j;
+    const int slot0 = (PW + (j >> 1) + 1) * 2 + (j & 1);  // region row 0 at plane row 1
+    if (ti < RPB && x >= 0 && x < n) {
+      for (int i0 = ti; i0 < R; i0 += RPB * kLoadBatch) {
+        uint4 v[kLoadBatch];
+        bool ok[kLoadBatch];
 #pragma unroll
-    for (int q = 0; q < kLoadBatch; ++q) {
-      const int e = e0 + q * kTbThreads + tid;
-      slot[q] = -1;
-      v[q] = make_uint4(0u, 0u, 0u, 0u);
-      if (e < R * CHL) {
-        const int i = e / CHL, j = jlo + (e - (e / CHL) * CHL);
-        const int y = yr0 + i, x = X0 - 32 + 16 * j;
-        if (y >= 0 && y < n && x >= 0 && x < n && (x & y) == 0) {
-          v[q] = *reinterpret_cast<const uint4 *>(mem.src(y, x));
-          slot[q] = ((i + 1) * PW + ((j >> 1) + 1)) * 2 + (j & 1);
+        for (int q = 0; q < kLoadBatch; ++q) {
+          const int i = i0 + q * RPB, y = yr0 + i;
+          ok[q] = i < R && (uint32_t)y < (uint32_t)n && (x & y) == 0;
+          // a defined value either way keeps each load in its own registers,
+          // so the batch's loads stay in flight together
+          v[q] = ok[q] ? *reinterpret_cast<const uint4 *>(mem.src(y, x)) : make_uint4(0u, 0u, 0u, 0u);
         }
+#pragma unroll
+        for (int q = 0; q < kLoadBatch; ++q)
+          if (ok[q]) p0h[slot0 + (i0 + q * RPB) * (2 * PW)] = (uint16_t)pack16(v[q]);
       }
     }
-#pragma unroll
-    for (int q = 0; q < kLoadBatch; ++q)
-      if (slot[q] >= 0) p0h[slot[q]] = (uint16_t)pack16(v[q]);
   }
 
   // 2. compact list of the segments (word column w, rows [b*L, b*L+L)) that
@@ -254,11 +275,12 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   //    whose word starts on the gasket (then its cells are exactly those of
   //    the row's pattern)
   const int lane = __lane_id();
+  const uint32_t nb_magic = div_small_magic((uint32_t)NB);
   for (int base = 0; base < W * NB; base += kTbThreads) {
     const int e = base + tid;
     uint32_t rows = 0u, code = 0u;
     if (e < W * NB) {
-      const int w = e / NB, b = e - (e / NB) * NB;
+      const int w = div_small(e, nb_magic), b = e - w * NB;
       const int xw = X0 - 32 + 32 * w;
       if (xw >= 0 && xw < n) {
 #pragma unroll
@@ -352,7 +374,7 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__
     bx = (uint32_t)(t & ((1ull << rb) - 1ull));
     if ((bx & by) != 0u) return;
   }
-  tb_tile<RHO, tb_threads<RHO>()>(DenseMem{in, out, 1 << r}, r, bx, by, T, lds, &nseg);
+  tb_tile<RHO, tb_threads<RHO>()>(DenseMem{in, out, r}, r, bx, by, T, lds, &nseg);
 }
 
 // One workgroup per tile of a gasket in block-compacted storage (lambda
@@ -393,12 +415,12 @@ __global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restric
     uint32_t bx, by;
     pass_decode((uint32_t)(g - it.tile_begin), it.r - it.k, bx, by);
     if (it.k == 6) {
-      tb_tile<64, NT>(DenseMem{it.src, it.dst, 1 << it.r}, it.r, bx, by, it.steps, lds, &nseg);
+      tb_tile<64, NT>(DenseMem{it.src, it.dst, it.r}, it.r, bx, by, it.steps, lds, &nseg);
     } else if (MAXRHO >= 128 && it.k == 7) {
-      tb_tile<(MAXRHO >= 128 ? 128 : 64), NT>(DenseMem{it.src, it.dst, 1 << it.r}, it.r, bx, by,
+      tb_tile<(MAXRHO >= 128 ? 128 : 64), NT>(DenseMem{it.src, it.dst, it.r}, it.r, bx, by,
                                               it.steps, lds, &nseg);
     } else if (MAXRHO >= 256 && it.k == 8) {
-      tb_tile<(MAXRHO >= 256 ? 256 : 64), NT>(DenseMem{it.src, it.dst, 1 << it.r}, it.r, bx, by,
+      tb_tile<(MAXRHO >= 256 ? 256 : 64), NT>(DenseMem{it.src, it.dst, it.r}, it.r, bx, by,
                                               it.steps, lds, &nseg);
     }
     __syncthreads();  // the next tile reuses the LDS planes
