@@ -123,15 +123,14 @@ __device__ __forceinline__ RowSums row_sums(uint32_t left, uint32_t mid, uint32_
 }
 
 // B3/S23 for 32 cells from the sums of the rows above (u), at (m) and below
-// (d), masked to the gasket cells `mask0 & mask1`.  With S the 3 x 3 sum
+// (d), masked to the gasket cells `mask`.  With S the 3 x 3 sum
 // (centre included) a cell lives next iff S == 3, or S == 4 and it is alive.
 // Writing S = s0 + 2 (a + k) + 4 b, where (s0, k) are the sum and carry of
 // the three lsb planes and (a, b) those of the three msb planes:
 //   S == 3  iff  s0 and not b and (a xor k),
 //   S == 4  iff  not s0 and ((not b, a, k) or (b, not a, not k)).
 __device__ __forceinline__ uint32_t life_rule(const RowSums &u, const RowSums &m,
-                                              const RowSums &d, uint32_t mask0,
-                                              uint32_t mask1) {
+                                              const RowSums &d, uint32_t mask) {
   const uint32_t s0 = bop3<kXor3>(u.h0, m.h0, d.h0);
   const uint32_t k = bop3<kMaj3>(u.h0, m.h0, d.h0);
   const uint32_t a = bop3<kXor3>(u.h1, m.h1, d.h1);
@@ -139,8 +138,7 @@ __device__ __forceinline__ uint32_t life_rule(const RowSums &u, const RowSums &m
   const uint32_t e3 = bop3<~kA & (kB ^ kC)>(b, a, k);                         // rest of S == 3
   const uint32_t e4 = bop3<(~kA & kB & kC) | (kA & ~kB & ~kC)>(b, a, k);      // rest of S == 4
   const uint32_t f = bop3<(kA & kB) | (~kA & kC)>(s0, e3, e4);                // s0 ? e3 : e4
-  const uint32_t g = bop3<kA & (kB | kC)>(f, s0, m.self);                     // f & (s0 | self)
-  return bop3<kA & kB & kC>(g, mask0, mask1);
+  return bop3<kA & (kB | kC)>(f, s0, m.self) & mask;                          // f & (s0 | self)
 }
 
 // Where a tile pass reads and writes cells.
@@ -209,7 +207,7 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   constexpr int L = kSegRows;
   static_assert(L <= 8, "row bits of a segment are kept in 8 bits");
   static_assert(RHO % 32 == 0, "tile rows are whole 32-cell words");
-  constexpr int NBMAX = (RHO + 2 * kMaxStepsPerPass + L - 1) / L;
+  constexpr int NBMAX = (RHO + 2 * kMaxStepsPerPass + L - 1) / L;  // segment blocks, T = 32
   static_assert((RHO + 2 + L - 1) / L >= 4 && W * NBMAX * (NBMAX - 1) < (1 << 20),
                 "div_small covers the segment list's e / NB");
   constexpr int G = RHO >= 64 ? 64 : RHO;  // store granule: 64 bytes, or the whole row
@@ -301,7 +299,32 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   __syncthreads();
   const int ns = (int)nseg;
 
-  // 3. T generations in LDS, one vertical segment per thread at a time
+  // 3. T generations in LDS.  Thread tid owns segments tid, tid + NT, ... of
+  //    the list for the whole pass; their plane index and the gasket mask of
+  //    each row (the row's pattern where the word starts on the gasket, else
+  //    0) are found once, into registers.
+  constexpr int KSEG = (W * NBMAX + kTbThreads - 1) / kTbThreads;  // list slots per thread
+  int sidx[KSEG], si0[KSEG], sw[KSEG];
+  uint32_t smask[KSEG][L];
+#pragma unroll
+  for (int kk = 0; kk < KSEG; ++kk) {
+    const int k = tid + kk * kTbThreads;
+    sidx[kk] = 0;
+    si0[kk] = R;  // no generation's rows reach region row R
+    sw[kk] = 0;
+#pragma unroll
+    for (int q = 0; q < L; ++q) smask[kk][q] = 0u;
+    if (k < ns) {
+      const uint32_t code = segs[k];
+      const int w = (int)(code & 0xffu), i0 = (int)((code >> 8) & 0xffu) * L;
+      const uint32_t rows = code >> 16;
+      sidx[kk] = (i0 + 1) * PW + (w + 1);
+      si0[kk] = i0;
+      sw[kk] = w;
+#pragma unroll
+      for (int q = 0; q < L; ++q) smask[kk][q] = ((rows >> q) & 1u) ? rowpat[i0 + q] : 0u;
+    }
+  }
   for (int s = 0; s < T; ++s) {
     const uint32_t *src = (s & 1) ? plane1 : plane0;
     uint32_t *dst = (s & 1) ? plane0 : plane1;
@@ -309,15 +332,15 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
     // region rows [s+1, R-s-1), and the halo words only while T-s-1 >= 1
     const int lo_row = s + 1, hi_row = R - s - 1;
     const uint32_t w_lo = s + 1 < T ? 0u : 1u, w_span = W - 1 - 2 * w_lo;
-    for (int k = tid; k < ns; k += kTbThreads) {
-      const uint32_t code = segs[k];
-      const int w = (int)(code & 0xffu), i0 = (int)((code >> 8) & 0xffu) * L;
+#pragma unroll
+    for (int kk = 0; kk < KSEG; ++kk) {
+      if (kk * kTbThreads >= ns) break;  // no thread holds a segment here (uniform)
+      const int i0 = si0[kk], w = sw[kk];
       if (i0 + L <= lo_row || i0 >= hi_row || (uint32_t)w - w_lo > w_span) continue;
-      const uint32_t rows = code >> 16;
-      const int idx0 = (i0 + 1) * PW + (w + 1);
+      const int idx0 = sidx[kk];
       // all rows the segment reads, before any store (the planes may alias as
       // far as the compiler knows, so loads are not moved past stores)
-      uint32_t row[L + 2][3], pat[L];
+      uint32_t row[L + 2][3];
 #pragma unroll
       for (int q = 0; q < L + 2; ++q) {
         const uint32_t *p = src + idx0 + (q - 1) * PW;
@@ -325,15 +348,12 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
         row[q][1] = p[0];
         row[q][2] = p[1];
       }
-#pragma unroll
-      for (int q = 0; q < L; ++q) pat[q] = rowpat[i0 + q];
       RowSums up = row_sums(row[0][0], row[0][1], row[0][2]);
       RowSums mid = row_sums(row[1][0], row[1][1], row[1][2]);
 #pragma unroll
       for (int q = 0; q < L; ++q) {
         const RowSums dn = row_sums(row[q + 2][0], row[q + 2][1], row[q + 2][2]);
-        const uint32_t on = 0u - ((rows >> q) & 1u);
-        dst[idx0 + q * PW] = life_rule(up, mid, dn, pat[q], on);
+        dst[idx0 + q * PW] = life_rule(up, mid, dn, smask[kk][q]);
         up = mid;
         mid = dn;
       }
