@@ -325,6 +325,7 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
       for (int q = 0; q < L; ++q) smask[kk][q] = ((rows >> q) & 1u) ? rowpat[i0 + q] : 0u;
     }
   }
+  const int wave0 = __builtin_amdgcn_readfirstlane(tid) & ~63;  // the wave's first thread
   for (int s = 0; s < T; ++s) {
     const uint32_t *src = (s & 1) ? plane1 : plane0;
     uint32_t *dst = (s & 1) ? plane0 : plane1;
@@ -334,7 +335,8 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
     const uint32_t w_lo = s + 1 < T ? 0u : 1u, w_span = W - 1 - 2 * w_lo;
 #pragma unroll
     for (int kk = 0; kk < KSEG; ++kk) {
-      if (kk * kTbThreads >= ns) break;  // no thread holds a segment here (uniform)
+      if (wave0 + kk * kTbThreads >= ns) break;  // this wave holds no segment here
+
       const int i0 = si0[kk], w = sw[kk];
       if (i0 + L <= lo_row || i0 >= hi_row || (uint32_t)w - w_lo > w_span) continue;
       const int idx0 = sidx[kk];
@@ -362,17 +364,23 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   }
   const uint16_t *fin = reinterpret_cast<const uint16_t *>((T & 1) ? plane1 : plane0);
 
-  // 4. unpack and store the tile, whole granules (64 bytes, or a 32-byte row)
-  constexpr int TC = RHO / 16;
-  for (int e = tid; e < RHO * TC; e += kTbThreads) {
-    const int ty = e / TC, j = e - (e / TC) * TC;
-    const int y = Y0 + ty, x = X0 + 16 * j;
-    // the embedding keeps granules without a gasket cell untouched; a compact
-    // tile is rewritten whole
-    if (!Mem::kCompact && ((x & ~(G - 1)) & y) != 0) continue;
+  // 4. unpack and store the tile, whole granules (64 bytes, or a 32-byte row).
+  //    Thread tid takes chunk column tid % TC of tile rows tid / TC, + RPS, ...
+  constexpr int TC = RHO / 16;          // 16-byte chunks per tile row
+  constexpr int RPS = kTbThreads / TC;  // tile rows per round
+  static_assert(kTbThreads % TC == 0, "the store rounds cover whole rows");
+  {
+    const int j = tid % TC, x = X0 + 16 * j;
     const int w = 1 + (j >> 1), half = j & 1;  // region chunk j + 2
-    const uint32_t bits = fin[((T + ty + 1) * PW + (w + 1)) * 2 + half];
-    *reinterpret_cast<uint4 *>(mem.dst(y, x)) = unpack16(bits);
+    const int f0 = ((T + 1) * PW + (w + 1)) * 2 + half;
+    for (int ty = tid / TC; ty < RHO; ty += RPS) {
+      const int y = Y0 + ty;
+      // the embedding keeps granules without a gasket cell untouched; a
+      // compact tile is rewritten whole
+      if (!Mem::kCompact && ((x & ~(G - 1)) & y) != 0) continue;
+      const uint32_t bits = fin[f0 + ty * (2 * PW)];
+      *reinterpret_cast<uint4 *>(mem.dst(y, x)) = unpack16(bits);
+    }
   }
 }
 
