@@ -1,11 +1,13 @@
-"""Code-generation guard for the temporally blocked life pass (no GPU needed).
+"""Code-generation guards for the temporally blocked passes (no GPU needed).
 
 The tile pass keeps a batch of region loads in flight per thread before it
 bit-packs any of them.  If the compiler moves work that uses a loaded value
 into the load's own conditional block, it has to wait for that load there
 (`s_waitcnt vmcnt(0)` right after it) and the batch is serialised, which cost
-8 % of the pass at rho = 256 when it happened.  This test compiles the pass to
-gfx950 assembly and checks that no region load is waited on inside its block.
+8 % of the pass at rho = 256 when it happened.  These tests compile the passes
+to gfx950 assembly and check that no life region load is waited on inside its
+block, and that the diffusion pass issues all its region loads before its
+first wait on them (it lists its chunks meanwhile).
 """
 import os
 import re
@@ -69,3 +71,28 @@ def test_guard_detects_a_serialised_batch():
     assert _waited_at_once(lines) == 1
     ok = ["global_load_dwordx4 v[6:9], v[2:3], off", ".LBB0_2:", "s_waitcnt vmcnt(0)"]
     assert _waited_at_once(ok) == 0
+
+
+@pytest.fixture(scope="module")
+def diffuse_asm(tmp_path_factory):
+    if not os.path.exists(B.HIPCC):
+        pytest.skip("hipcc is not available")
+    out = tmp_path_factory.mktemp("asm") / "sg_diffuse_tb.s"
+    src = os.path.join(B.CSRC, "sg_diffuse_tb.hip")
+    cmd = [B.HIPCC, *B.HIP_FLAGS, "--cuda-device-only", "-S", src, "-o", str(out)]
+    subprocess.run(cmd, check=True, stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    return out.read_text()
+
+
+def test_diffusion_tile_pass_issues_all_region_loads_before_waiting(diffuse_asm):
+    # the diffusion pass lists its chunks while every region load is in flight
+    names = re.findall(r"^(_Z\w*k_diffuse_tb\w*):", diffuse_asm, re.M)
+    assert len(names) == 6  # rho 16, 32, 64 for both maps
+    for name in names:
+        start = diffuse_asm.index(name + ":")
+        end = diffuse_asm.index(".Lfunc_end", start)
+        lines = [l.strip() for l in diffuse_asm[start:end].split("\n")]
+        lines = [l for l in lines if l and not l.startswith(";")]
+        loads = [i for i, l in enumerate(lines) if re.match(r"global_load_dwordx4\b", l)]
+        assert loads, name
+        assert not [l for l in lines[loads[0]:loads[-1]] if "vmcnt" in l], name
