@@ -300,18 +300,21 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   const int ns = (int)nseg;
 
   // 3. T generations in LDS.  Thread tid owns segments tid, tid + NT, ... of
-  //    the list for the whole pass; their plane index and the gasket mask of
-  //    each row (the row's pattern where the word starts on the gasket, else
-  //    0) are found once, into registers.
+  //    the list for the whole pass; their plane index, the gasket mask of each
+  //    row (the row's pattern where the word starts on the gasket, else 0) and
+  //    the number of generations that need them are found once, into
+  //    registers.  Generation s needs the cells that can still reach the tile
+  //    in the T-s-1 generations left: region rows [s+1, R-s-1), and the halo
+  //    words only while T-s-1 >= 1; so a segment of rows [i0, i0+L) is needed
+  //    while s < min(i0 + L - 1, R - 1 - i0, T, or T - 1 for a halo word).
   constexpr int KSEG = (W * NBMAX + kTbThreads - 1) / kTbThreads;  // list slots per thread
-  int sidx[KSEG], si0[KSEG], sw[KSEG];
+  int sidx[KSEG], slim[KSEG];
   uint32_t smask[KSEG][L];
 #pragma unroll
   for (int kk = 0; kk < KSEG; ++kk) {
     const int k = tid + kk * kTbThreads;
     sidx[kk] = 0;
-    si0[kk] = R;  // no generation's rows reach region row R
-    sw[kk] = 0;
+    slim[kk] = 0;  // an empty slot is needed by no generation
 #pragma unroll
     for (int q = 0; q < L; ++q) smask[kk][q] = 0u;
     if (k < ns) {
@@ -319,8 +322,8 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
       const int w = (int)(code & 0xffu), i0 = (int)((code >> 8) & 0xffu) * L;
       const uint32_t rows = code >> 16;
       sidx[kk] = (i0 + 1) * PW + (w + 1);
-      si0[kk] = i0;
-      sw[kk] = w;
+      const int span = (w == 0 || w == W - 1) ? T - 1 : T;
+      slim[kk] = min(span, min(i0 + L - 1, R - 1 - i0));
 #pragma unroll
       for (int q = 0; q < L; ++q) smask[kk][q] = ((rows >> q) & 1u) ? rowpat[i0 + q] : 0u;
     }
@@ -329,16 +332,10 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   for (int s = 0; s < T; ++s) {
     const uint32_t *src = (s & 1) ? plane1 : plane0;
     uint32_t *dst = (s & 1) ? plane0 : plane1;
-    // cells that can still reach the tile in the T-s-1 generations left:
-    // region rows [s+1, R-s-1), and the halo words only while T-s-1 >= 1
-    const int lo_row = s + 1, hi_row = R - s - 1;
-    const uint32_t w_lo = s + 1 < T ? 0u : 1u, w_span = W - 1 - 2 * w_lo;
 #pragma unroll
     for (int kk = 0; kk < KSEG; ++kk) {
       if (wave0 + kk * kTbThreads >= ns) break;  // this wave holds no segment here
-
-      const int i0 = si0[kk], w = sw[kk];
-      if (i0 + L <= lo_row || i0 >= hi_row || (uint32_t)w - w_lo > w_span) continue;
+      if (s >= slim[kk]) continue;               // cannot reach the tile any more
       const int idx0 = sidx[kk];
       // all rows the segment reads, before any store (the planes may alias as
       // far as the compiler knows, so loads are not moved past stores)
