@@ -35,6 +35,7 @@ def _load():
         "sgo_member_paper": (_int, [_i64, _i64, _i64]),
         "sgo_count_cells": (_i64, [_int]),
         "sgo_threads": (_int, []),
+        "sgo_set_threads": (None, [_int]),
         "sgo_lambda_grid": (None, [_int, _ptr, _ptr]),
         "sgo_lambda": (None, [_int, _i64, _i64, _ptr, _ptr]),
         "sgo_map_lambda": (None, [_int, _ptr]),
@@ -42,10 +43,13 @@ def _load():
         "sgo_write_pass": (None, [_int, ctypes.c_uint8, _ptr]),
         "sgo_life_step_plain": (None, [_i64, _i64, _ptr, _ptr]),
         "sgo_life_step": (None, [_int, _ptr, _ptr]),
+        "sgo_life_step_sparse": (None, [_int, _ptr, _ptr]),
         "sgo_life_window": (None, [_int, _ptr, _i64, _i64, _i64, _i64, _int, _ptr]),
         "sgo_life_region": (None, [_i64, _i64, _i64, _i64, _int, _ptr]),
         "sgo_row_checksums": (None, [_int, _ptr, _ptr, _ptr]),
         "sgo_diffuse_step": (None, [_int, _ptr, _ptr, ctypes.c_double]),
+        "sgo_gasket_graph": (None, [_int, _ptr, _ptr]),
+        "sgo_diffuse_step_graph": (None, [_i64, _ptr, _ptr, _ptr, ctypes.c_double]),
         "sgo_diffuse_window": (None, [_int, _ptr, _i64, _i64, _i64, _i64, _int,
                                       ctypes.c_double, _ptr]),
         "sgo_map_lambda_rect": (None, [_int, _int, _int, _ptr]),
@@ -54,6 +58,8 @@ def _load():
         "sgo_frac_lambda": (None, [_int, _int, _ptr, _ptr, _int, _i64, _i64, _ptr, _ptr]),
         "sgo_frac_map": (None, [_int, _int, _ptr, _ptr, _int, _ptr]),
         "sgo_frac_write": (None, [_int, _int, _ptr, _ptr, _int, ctypes.c_uint8, _ptr]),
+        "sgo_frac_write_rows": (None, [_int, _int, _ptr, _ptr, _int, ctypes.c_uint8, _i64, _i64,
+                                       _ptr]),
         "sgo_frac_life_step": (None, [_int, _int, _ptr, _ptr, _int, _ptr, _ptr]),
         "sgo_frac_life_window": (None, [_int, _int, _ptr, _ptr, _int, _ptr, _i64, _i64, _i64,
                                         _i64, _int, _ptr]),
@@ -81,6 +87,11 @@ def _check_state(r: int, a: np.ndarray, dtype):
 def threads() -> int:
     """Threads the oracle's OpenMP row loops use."""
     return int(_load().sgo_threads())
+
+
+def set_threads(t: int) -> None:
+    """Threads for the OpenMP row loops from now on."""
+    _load().sgo_set_threads(int(t))
 
 
 # ---------------------------------------------------------------- membership
@@ -184,6 +195,34 @@ def life_steps(r: int, a: np.ndarray, steps: int) -> np.ndarray:
     return cur
 
 
+def life_step_sparse(r: int, a: np.ndarray) -> np.ndarray:
+    """One step visiting only the gasket's cells (same result as life_step)."""
+    a = _check_state(r, a, np.uint8)
+    out = np.zeros_like(a)
+    _load().sgo_life_step_sparse(r, _p(a), _p(out))
+    return out
+
+
+def life_steps_sparse(r: int, a: np.ndarray, steps: int, snapshots=()) -> np.ndarray:
+    """`steps` steps visiting only the gasket's cells (same result as
+    life_steps).  With `snapshots`, returns {t: state after t steps} for each
+    t listed (0 <= t <= steps) instead."""
+    a = _check_state(r, a, np.uint8)
+    cur = a.copy()
+    nxt = np.zeros_like(a)  # cells off the gasket stay 0
+    lib = _load()
+    want = sorted(set(int(t) for t in snapshots))
+    shots = {}
+    if 0 in want:
+        shots[0] = cur.copy()
+    for t in range(1, steps + 1):
+        lib.sgo_life_step_sparse(r, _p(cur), _p(nxt))
+        cur, nxt = nxt, cur
+        if t in want:
+            shots[t] = cur.copy() if t != steps else cur
+    return shots if want else cur
+
+
 def life_window(r: int, a: np.ndarray, x0: int, y0: int, w: int, h: int,
                 steps: int) -> np.ndarray:
     """State after `steps` on the window [x0, x0+w) x [y0, y0+h)."""
@@ -230,6 +269,46 @@ def diffuse_steps(r: int, u0: np.ndarray, steps: int, alpha: float = 0.2) -> np.
         lib.sgo_diffuse_step(r, _p(cur), _p(nxt), alpha)
         cur, nxt = nxt, cur
     return cur
+
+
+def gasket_graph(r: int):
+    """The gasket's cells in row-major order and their 4-neighbours:
+    pos[i] = y * n + x of cell i; nb[i, k] = the number of its neighbour
+    k = W, E, N, S, or -1 (off the grid or off the gasket).  r <= 19."""
+    if not 0 <= r <= 19:
+        raise ValueError("gasket_graph numbers cells in int32: r <= 19")
+    N = 3 ** r
+    pos = np.empty(N, dtype=np.int64)
+    nb = np.empty(4 * N, dtype=np.int32)
+    _load().sgo_gasket_graph(r, _p(pos), _p(nb))
+    return pos, nb.reshape(N, 4)
+
+
+def diffuse_steps_graph(r: int, u0: np.ndarray, steps: int, alpha: float = 0.2,
+                        snapshots=()):
+    """FP64 diffusion over the gasket graph from an n x n field (FP32 or
+    FP64): the sum of diffuse_step term for term, so the gasket cells' values
+    are identical to diffuse_steps'.  Returns (pos, u) with u[i] the value of
+    the cell at flat position pos[i] after `steps` steps, or (pos, {t: u})
+    for the steps listed in `snapshots`."""
+    n = 1 << r
+    u0 = np.ascontiguousarray(u0)
+    if u0.shape != (n, n):
+        raise ValueError(f"expected shape ({n}, {n})")
+    pos, nb = gasket_graph(r)
+    cur = u0.reshape(-1)[pos].astype(np.float64)
+    nxt = np.empty_like(cur)
+    lib = _load()
+    want = sorted(set(int(t) for t in snapshots))
+    shots = {}
+    if 0 in want:
+        shots[0] = cur.copy()
+    for t in range(1, steps + 1):
+        lib.sgo_diffuse_step_graph(len(cur), _p(nb), _p(cur), _p(nxt), alpha)
+        cur, nxt = nxt, cur
+        if t in want:
+            shots[t] = cur.copy()
+    return pos, (shots if want else cur)
 
 
 def diffuse_window(r: int, u0: np.ndarray, x0: int, y0: int, w: int, h: int,
@@ -287,6 +366,14 @@ def frac_write(f: Fractal, r: int, value: int) -> np.ndarray:
     a = np.zeros((n, n), dtype=np.uint8)
     _load().sgo_frac_write(*f.args(), r, value, _p(a))
     return a
+
+
+def frac_write_rows(f: Fractal, r: int, value: int, y0: int, rows: int) -> np.ndarray:
+    """Rows [y0, y0 + rows) of frac_write(f, r, value)."""
+    n = f.n(r)
+    out = np.zeros((rows, n), dtype=np.uint8)
+    _load().sgo_frac_write_rows(*f.args(), r, value, y0, rows, _p(out))
+    return out
 
 
 def frac_life_steps(f: Fractal, r: int, a: np.ndarray, steps: int) -> np.ndarray:

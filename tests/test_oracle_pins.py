@@ -546,3 +546,82 @@ def test_life_region_equals_full_run(r, steps):
         reg = O.life_region(gx0, gy0, a0[gy0:gy1, gx0:gx1], steps)
         assert np.array_equal(reg[y0 - gy0:y0 - gy0 + h, x0 - gx0:x0 - gx0 + w],
                               full[y0:y0 + h, x0:x0 + w]), (x0, y0)
+
+
+# ------------------------------------------------------------------ gasket-only formulations
+
+def test_sparse_life_equals_dense_on_every_state_r2():
+    # all 2^9 states of the 9 gasket cells at r = 2
+    r, n = 2, 4
+    mask = recursive_gasket(r)
+    cells = list(zip(*np.nonzero(mask)))
+    assert len(cells) == 9
+    for bits in range(1 << 9):
+        a = np.zeros((n, n), dtype=np.uint8)
+        for i, (y, x) in enumerate(cells):
+            a[y, x] = (bits >> i) & 1
+        assert np.array_equal(O.life_step_sparse(r, a), O.life_step(r, a)), bits
+
+
+@pytest.mark.parametrize("r,p,steps", [(0, 0.5, 3), (1, 0.9, 3), (3, 0.5, 6), (5, 0.3, 9),
+                                       (7, 0.5, 12), (9, 0.7, 8), (10, 0.5, 20)])
+def test_sparse_life_equals_dense(r, p, steps):
+    a0 = inputs.bernoulli_state(r, p, 40 + r)
+    assert np.array_equal(O.life_steps_sparse(r, a0, steps), O.life_steps(r, a0, steps))
+    shots = O.life_steps_sparse(r, a0, steps, snapshots=(0, 1, steps))
+    assert np.array_equal(shots[0], a0)
+    assert np.array_equal(shots[1], O.life_step(r, a0))
+    assert np.array_equal(shots[steps], O.life_steps(r, a0, steps))
+
+
+@pytest.mark.parametrize("r", [0, 1, 2, 5, 8])
+def test_gasket_graph_is_the_gasket_adjacency(r):
+    n = 1 << r
+    pos, nb = O.gasket_graph(r)
+    mask = recursive_gasket(r)
+    assert np.array_equal(pos, np.flatnonzero(mask.ravel()))  # row-major gasket cells
+    x, y = pos % n, pos // n
+    for k, (dx, dy) in enumerate(((-1, 0), (1, 0), (0, -1), (0, 1))):
+        xx, yy = x + dx, y + dy
+        ok = (xx >= 0) & (xx < n) & (yy >= 0) & (yy < n)
+        ok[ok] &= mask[yy[ok], xx[ok]]
+        assert np.array_equal(nb[:, k] >= 0, ok)
+        assert np.array_equal(pos[nb[ok, k]], yy[ok] * n + xx[ok])
+    # W and E, N and S are each other's inverse
+    for k, kk in ((0, 1), (2, 3)):
+        has = nb[:, k] >= 0
+        assert np.array_equal(nb[nb[has, k], kk], np.flatnonzero(has))
+
+
+@pytest.mark.parametrize("r,steps", [(0, 2), (2, 5), (6, 17), (9, 11)])
+def test_graph_diffusion_equals_dense_bit_for_bit(r, steps):
+    u0 = inputs.uniform_field(r, 60 + r)
+    dense = O.diffuse_steps(r, u0, steps).reshape(-1)
+    pos, u = O.diffuse_steps_graph(r, u0, steps)
+    assert np.array_equal(u, dense[pos])
+    assert not dense[np.setdiff1d(np.arange(dense.size), pos)].any()
+    _, shots = O.diffuse_steps_graph(r, u0, steps, snapshots=(0, 1, steps))
+    assert np.array_equal(shots[0], u0.reshape(-1)[pos].astype(np.float64))
+    assert np.array_equal(shots[1], O.diffuse_steps(r, u0, 1).reshape(-1)[pos])
+    assert np.array_equal(shots[steps], u)
+
+
+@pytest.mark.parametrize("name,r", [("carpet", 4), ("vicsek", 5), ("gasket", 6)])
+def test_fractal_write_rows_are_rows_of_the_write_pass(name, r):
+    f = {"carpet": O.CARPET, "vicsek": O.VICSEK, "gasket": O.GASKET}[name]
+    full = O.frac_write(f, r, 7)
+    n = f.n(r)
+    for y0, rows in ((0, 1), (3, 5), (n - 4, 4)):
+        assert np.array_equal(O.frac_write_rows(f, r, 7, y0, rows), full[y0:y0 + rows])
+
+
+def test_set_threads_changes_no_result():
+    a0 = inputs.bernoulli_state(9, 0.5, 5)
+    t = O.threads()
+    try:
+        O.set_threads(1)
+        assert O.threads() == 1
+        one = O.life_steps_sparse(9, a0, 7)
+    finally:
+        O.set_threads(t)
+    assert np.array_equal(one, O.life_steps_sparse(9, a0, 7))
