@@ -137,11 +137,13 @@ SG_API int sg_ca_step(int map, int r, int rho, const uint8_t *d_in,
                       uint8_t *d_out, void *stream);
 
 /* `steps` generations of the life step above (sg_ca_step), with the result
- * left in d_out.  The generations run in passes of up to `steps_per_pass`
- * generations each: a pass reads its tile plus a halo of that many cells
- * from HBM once, runs the generations on chip and writes the tile once
- * (temporal blocking), so HBM traffic per generation falls by that factor.
- * The result is identical to `steps` calls of sg_ca_step.
+ * left in d_out.  The generations run in ceil(steps / steps_per_pass)
+ * passes that split them as evenly as possible (each runs floor or ceil of
+ * steps / passes, at most `steps_per_pass`): a pass reads its tile plus a
+ * halo of as many cells as its generations from HBM once, runs the
+ * generations on chip and writes the tile once (temporal blocking), so HBM
+ * traffic per generation falls by that factor.  The result is identical to
+ * `steps` calls of sg_ca_step.
  *   steps_per_pass: 1 (one launch per generation, any rho), 2..32 (rho in
  *     {32, 64, 128, 256}), 2..16 (rho = 16), or 0 for the library's choice
  *     (the largest where supported, else 1).
@@ -169,8 +171,9 @@ SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in,
                            float *d_out, float alpha, void *stream);
 
 /* `steps` diffusion steps (sg_diffuse_step) with the result in d_out, in
- * passes of up to `steps_per_pass` steps: a pass reads its tile plus a halo
- * of that many cells from HBM once and runs the steps on chip (temporal
+ * ceil(steps / steps_per_pass) passes that split the steps as evenly as
+ * possible (as sg_ca_steps): a pass reads its tile plus a halo of as many
+ * cells as its steps from HBM once and runs the steps on chip (temporal
  * blocking).  Every cell update is the same FP32 arithmetic as
  * sg_diffuse_step, so the result equals `steps` calls of it bit for bit.
  *   steps_per_pass: 1 (one launch per step, any rho), 2..8 (rho in {16, 32, 64}),
@@ -216,7 +219,8 @@ SG_API int sg_compact_init_bernoulli(int r, int rho, uint64_t seed, uint64_t thr
                                      uint8_t *d_compact, void *stream);
 
 /* sg_ca_steps on compact states (lambda map): `steps` life generations
- * from d_in into d_out, up to `steps_per_pass` (1..32, 0 = 32) per pass;
+ * from d_in into d_out, in passes of at most `steps_per_pass` (1..32,
+ * 0 = 32) split as sg_ca_steps splits them;
  * every pass rewrites its output tiles whole, so d_out and d_work need no
  * zeroing.  All three: compact-sized, 16-byte aligned, non-overlapping.
  * Errors: SG_EINVAL, SG_EALIAS, SG_EHIP. */
@@ -396,6 +400,7 @@ SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
 /* Waits for the context's last upload and frees it (NULL is ignored). */
 SG_API void sg_pass_ctx_destroy(sg_pass_ctx *ctx);
 
+
 /* ---------------------------------------------------------------------
  * Continuous batching of life solves (a native serving loop over
  * sg_pass_run).  Requests are admitted first come first served while their
@@ -421,6 +426,11 @@ typedef struct sg_server_stats {
     uint64_t rounds, passes, completed, rejected, cell_steps;
     uint64_t max_resident_bytes, max_active;
     uint64_t queued, active, resident_bytes; /* now */
+    /* device bytes of the buffers the server holds (its pool, resident
+     * states and last round's results): now, and the most ever; never above
+     * the cap, since idle pooled buffers of other levels are freed before an
+     * allocation would pass it */
+    uint64_t allocated_bytes, max_allocated_bytes;
 } sg_server_stats;
 
 /* tune: the batched pass's launch shape (as sg_batch_create); max_requests:

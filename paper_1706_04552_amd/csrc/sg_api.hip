@@ -48,6 +48,16 @@ bool overlaps(const void *a, const void *b, size_t bytes) {
   return pa < pb + bytes && pb < pa + bytes;
 }
 
+// Steps of pass k (1-based) when `steps` are split over `passes` passes as
+// evenly as possible: every pass runs floor or ceil of steps / passes, the
+// longer ones last.  A pass costs a fixed part (load, list, store) plus a
+// part per step that grows with its halo, so an even split does the least
+// halo work for a given number of passes.
+int pass_steps(int steps, int passes, int k) {
+  const int q = steps / passes, rem = steps % passes;
+  return q + (k > passes - rem ? 1 : 0);
+}
+
 int pass_args(int map, int r, int rho, void *stream, sg::PassArgs &a) {
   const int rb = block_level(r, rho);
   if (rb < 0 || (map != SG_MAP_LAMBDA && map != SG_MAP_BBOX)) return SG_EINVAL;
@@ -185,7 +195,7 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
   const uint8_t *src = d_in;
   for (int k = 1; k <= passes; ++k) {
     uint8_t *dst = ((passes - k) % 2 == 0) ? d_out : d_work;
-    const int T = k < passes ? steps_per_pass : steps - (passes - 1) * steps_per_pass;
+    const int T = pass_steps(steps, passes, k);
     const hipError_t e = T == 1 && steps_per_pass == 1 ? sg::launch_life(a, src, dst)
                          : tb_ok                          ? sg::launch_life_tb(a, T, src, dst)
                                                           : sg::launch_life_tbs(a, T, src, dst);
@@ -220,7 +230,7 @@ SG_API int sg_diffuse_steps(int map, int r, int rho, int steps, int steps_per_pa
   const float *src = d_in;
   for (int k = 1; k <= passes; ++k) {
     float *dst = ((passes - k) % 2 == 0) ? d_out : d_work;
-    const int T = k < passes ? steps_per_pass : steps - (passes - 1) * steps_per_pass;
+    const int T = pass_steps(steps, passes, k);
     const hipError_t e = steps_per_pass == 1 ? sg::launch_diffuse(a, src, dst, alpha)
                                              : sg::launch_diffuse_tb(a, T, src, dst, alpha);
     if (e != hipSuccess) return hip_status(e);
@@ -306,7 +316,7 @@ SG_API int sg_ca_steps_compact(int r, int rho, int steps, int steps_per_pass,
   const uint8_t *src = d_in;
   for (int k = 1; k <= passes; ++k) {
     uint8_t *dst = ((passes - k) % 2 == 0) ? d_out : d_work;
-    const int T = k < passes ? steps_per_pass : steps - (passes - 1) * steps_per_pass;
+    const int T = pass_steps(steps, passes, k);
     const hipError_t e = sg::launch_life_tb_compact(a, T, src, dst);
     if (e != hipSuccess) return hip_status(e);
     src = dst;

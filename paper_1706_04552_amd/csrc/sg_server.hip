@@ -8,6 +8,7 @@
 // is used from one host thread.
 #include <string.h>
 
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <memory>
@@ -43,6 +44,8 @@ struct Req {
 struct sg_server {
   sg_tune tune;
   uint64_t cap, horizon, budget, used = 0;
+  uint64_t allocated = 0;      // device bytes of every buffer held (pool, resident, results)
+  uint64_t max_allocated = 0;
   int max_requests;
   hipStream_t stream;
   sg_pass_ctx *ctx = nullptr;
@@ -50,15 +53,54 @@ struct sg_server {
   std::vector<Req> active;                        // resident, in admission order
   std::map<int, std::vector<uint8_t *>> pool;     // free buffers by level
   std::vector<std::pair<int, uint8_t *>> held;    // last round's results, freed next round
-  std::vector<uint8_t *> owned;                   // every buffer ever allocated
+  std::vector<uint8_t *> owned;                   // every buffer allocated and not freed
   std::vector<sg_pass_item> items;
   sg_server_stats stats = {};
 };
 
 namespace {
 
-// A zeroed n x n buffer of level r: from the pool, or newly allocated (and
-// cleared, so it holds 0 off the gasket; passes never write there).
+uint64_t level_bytes(int r) { return 1ull << (2 * r); }
+
+// Frees idle pooled buffers of levels other than `keep` until `need` more
+// bytes fit under the cap.  Pooled buffers belong to requests retired by
+// earlier rounds, each of which ended with a device wait, so no queued work
+// uses them.
+void make_room(sg_server *s, int keep, uint64_t need) {
+  for (auto &kv : s->pool) {
+    if (kv.first == keep) continue;
+    auto &v = kv.second;
+    while (!v.empty() && s->allocated + need > s->cap) {
+      uint8_t *p = v.back();
+      v.pop_back();
+      (void)hipFree(p);
+      s->owned.erase(std::find(s->owned.begin(), s->owned.end(), p));
+      s->allocated -= level_bytes(kv.first);
+    }
+  }
+}
+
+// A fresh zeroed n x n buffer of level r (cleared, so it holds 0 off the
+// gasket; passes never write there), keeping the bytes held under the cap.
+int new_buffer(sg_server *s, int r, uint8_t **out) {
+  const uint64_t bytes = level_bytes(r);
+  make_room(s, r, bytes);
+  if (s->allocated + bytes > s->cap) return SG_ENOMEM;
+  uint8_t *p = nullptr;
+  if (hipMalloc((void **)&p, bytes) != hipSuccess) return SG_ENOMEM;
+  s->owned.push_back(p);
+  s->allocated += bytes;
+  if (s->allocated > s->max_allocated) s->max_allocated = s->allocated;
+  if (hipMemsetAsync(p, 0, bytes, s->stream) != hipSuccess) return SG_EHIP;
+  *out = p;
+  return SG_OK;
+}
+
+// A zeroed n x n buffer of level r: from the pool, or newly allocated.  The
+// admission test keeps the footprints of resident requests under the cap,
+// and buffers of other levels that sit idle in the pool are freed before an
+// allocation would take the bytes held past it, so the device memory the
+// server holds never exceeds the cap.
 int take_buffer(sg_server *s, int r, uint8_t **out) {
   auto &free = s->pool[r];
   if (!free.empty()) {
@@ -66,13 +108,7 @@ int take_buffer(sg_server *s, int r, uint8_t **out) {
     free.pop_back();
     return SG_OK;
   }
-  const size_t bytes = (size_t)1 << (2 * r);
-  uint8_t *p = nullptr;
-  if (hipMalloc((void **)&p, bytes) != hipSuccess) return SG_ENOMEM;
-  s->owned.push_back(p);
-  if (hipMemsetAsync(p, 0, bytes, s->stream) != hipSuccess) return SG_EHIP;
-  *out = p;
-  return SG_OK;
+  return new_buffer(s, r, out);
 }
 
 void release_held(sg_server *s) {
@@ -129,19 +165,18 @@ SG_API int sg_server_reserve(sg_server *s, const int32_t *levels, int count) {
     if (!s || count < 0 || (count > 0 && !levels)) return SG_EINVAL;
     for (int i = 0; i < count; ++i)
       if (levels[i] < kMinLevel || levels[i] > SG_MAX_R) return SG_EINVAL;
-    uint64_t total = 0;
-    for (auto &kv : s->pool) total += (uint64_t)kv.second.size() << (2 * kv.first);
     for (int i = 0; i < count; ++i) {
-      if (total + footprint(levels[i]) > s->cap) break;
+      if (s->allocated + footprint(levels[i]) > s->cap) break;
       for (int b = 0; b < 2; ++b) {
-        const size_t bytes = (size_t)1 << (2 * levels[i]);
+        const uint64_t bytes = level_bytes(levels[i]);
         uint8_t *p = nullptr;
         if (hipMalloc((void **)&p, bytes) != hipSuccess) return SG_ENOMEM;
         s->owned.push_back(p);
+        s->allocated += bytes;
+        if (s->allocated > s->max_allocated) s->max_allocated = s->allocated;
         if (hipMemsetAsync(p, 0, bytes, s->stream) != hipSuccess) return SG_EHIP;
         s->pool[levels[i]].push_back(p);
       }
-      total += footprint(levels[i]);
     }
     return hipStreamSynchronize(s->stream) == hipSuccess ? SG_OK : SG_EHIP;
   });
@@ -178,8 +213,12 @@ SG_API int sg_server_step(sg_server *s, sg_server_done *done, int max_done, int 
       }
       if (s->used + fp > s->cap) break;
       int st = take_buffer(s, q.r, &q.buf[0]);
-      if (st == SG_OK) st = take_buffer(s, q.r, &q.buf[1]);
       if (st != SG_OK) return st;
+      st = take_buffer(s, q.r, &q.buf[1]);
+      if (st != SG_OK) {
+        s->pool[q.r].push_back(q.buf[0]);  // stays owned, back in the pool
+        return st;
+      }
       if (hipMemcpyAsync(q.buf[0], q.init, (size_t)1 << (2 * q.r), hipMemcpyDeviceToDevice,
                          s->stream) != hipSuccess)
         return SG_EHIP;
@@ -256,6 +295,8 @@ SG_API int sg_server_get_stats(const sg_server *s, sg_server_stats *out) {
   out->queued = s->queue.size();
   out->active = s->active.size();
   out->resident_bytes = s->used;
+  out->allocated_bytes = s->allocated;
+  out->max_allocated_bytes = s->max_allocated;
   return SG_OK;
 }
 

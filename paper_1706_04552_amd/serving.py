@@ -190,47 +190,67 @@ class GpuExecutor:
     """Device-resident states and libsg's batched pass (one launch per
     iteration over all resident requests)."""
 
-    def __init__(self, tune, capacity: int = 4096, templates: Optional[Dict[int, object]] = None):
+    def __init__(self, tune, capacity: int = 4096, templates: Optional[Dict[int, object]] = None,
+                 cap_bytes: Optional[int] = None):
+        """cap_bytes: the scheduler's footprint cap; the buffers the executor
+        holds (pooled and resident) are kept under it by dropping idle pooled
+        buffers of other levels before a new one would pass it."""
         import torch
         from .batch import PassContext
         self.torch = torch
         self.tune = tune
         self.ctx = PassContext(capacity)
         self.templates = templates or {}
+        self.cap = cap_bytes
+        self.allocated = 0       # bytes of the buffers held, pooled or resident
+        self.max_allocated = 0
         # released buffers, by level: they hold 0 on every cell off the gasket
         # (passes never write there), which is all a destination needs
         self.pool: Dict[int, List[object]] = {}
 
+    def _new(self, r: int):
+        n = 1 << r
+        t = self.torch.zeros((n, n), dtype=self.torch.uint8, device="cuda")
+        self.allocated += n * n
+        self.max_allocated = max(self.max_allocated, self.allocated)
+        return t
+
     def reserve(self, levels: Sequence[int], cap_bytes: int) -> int:
         """Pre-allocate the buffer pool, as a server sizes its memory at start:
-        two buffers per entry of `levels` (in order) while the total stays
-        under `cap_bytes`.  Returns the bytes reserved."""
-        total = 0
+        two buffers per entry of `levels` (in order) while the bytes held stay
+        under `cap_bytes`.  Returns the bytes held."""
         for r in levels:
-            fp = footprint(r)
-            if total + fp > cap_bytes:
+            if self.allocated + footprint(r) > cap_bytes:
                 break
-            n = 1 << r
-            self.pool.setdefault(r, []).extend(
-                self.torch.zeros((n, n), dtype=self.torch.uint8, device="cuda") for _ in range(2))
-            total += fp
-        return total
+            self.pool.setdefault(r, []).extend(self._new(r) for _ in range(2))
+        return self.allocated
 
     def _buffer(self, r: int):
         free = self.pool.get(r)
         if free:
             return free.pop()
-        n = 1 << r
-        return self.torch.zeros((n, n), dtype=self.torch.uint8, device="cuda")
+        need = (1 << r) * (1 << r)
+        if self.cap is not None:
+            # idle buffers of other levels go first (the scheduler's
+            # admission test keeps resident footprints under the cap)
+            for lv, bufs in self.pool.items():
+                while lv != r and bufs and self.allocated + need > self.cap:
+                    bufs.pop()
+                    self.allocated -= (1 << lv) * (1 << lv)
+        return self._new(r)
 
     def admit(self, q: Request):
         from .batch import checked_ptr
         cur = self._buffer(q.r)
+        try:
+            nxt = self._buffer(q.r)
+        except Exception:
+            self.pool.setdefault(q.r, []).append(cur)
+            raise
         if q.template is not None:
             cur.copy_(self.templates[q.template])
         else:
             cur.copy_(self.torch.from_numpy(np.ascontiguousarray(q.state)))
-        nxt = self._buffer(q.r)
         return {"r": q.r, "buf": [cur, nxt],
                 "p": [checked_ptr(cur, q.r, "state"), checked_ptr(nxt, q.r, "state")]}
 

@@ -63,7 +63,8 @@ class sg_server_done(ctypes.Structure):
 class sg_server_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in
                 ("rounds", "passes", "completed", "rejected", "cell_steps", "max_resident_bytes",
-                 "max_active", "queued", "active", "resident_bytes")]
+                 "max_active", "queued", "active", "resident_bytes", "allocated_bytes",
+                 "max_allocated_bytes")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -45,8 +45,8 @@ def make_gaskets(count, r_lo, r_hi, steps_lo, steps_hi, seed):
 
 
 def oracle_check(r, a0, steps, got):
-    if r <= 9:
-        assert np.array_equal(got, O.life_steps(r, a0, steps) if steps else a0)
+    if r <= 11:
+        assert np.array_equal(got, O.life_steps_sparse(r, a0, steps) if steps else a0)
     else:
         n = 1 << r
         for (x0, y0) in [(0, 0), (n - 48, 0), (0, n - 8), (n // 3, n // 5)]:
@@ -169,7 +169,7 @@ def test_serving_results_equal_alone_and_respect_the_cap(horizon, budget):
 def test_batch_benchmark_configuration_every_instance():
     """The benchmark's batch: 512 gaskets (r ~ U{6..13}, p ~ U[0.2, 0.8]),
     50 generations, the autotuner's launch shape, one hipGraph; every
-    instance against the oracle (whole state for r <= 8, sampled windows
+    instance against the oracle (whole state for r <= 11, sampled windows
     from the dependency cone above)."""
     steps = 50
     specs = inputs.batch_specs(512)
@@ -186,8 +186,8 @@ def test_batch_benchmark_configuration_every_instance():
         torch.cuda.synchronize()
     for spec, g, a0 in zip(specs, gs, hosts):
         got = g.out.cpu().numpy()
-        if spec.r <= 8:
-            assert np.array_equal(got, O.life_steps(spec.r, a0, steps)), spec
+        if spec.r <= 11:
+            assert np.array_equal(got, O.life_steps_sparse(spec.r, a0, steps)), spec
         else:
             n = 1 << spec.r
             for (x0, y0) in [(0, 0), (n - 40, n // 2), (n // 3, n - 6)]:
@@ -246,3 +246,53 @@ def test_native_server_reuses_its_pool_across_waves():
         for q in reqs:
             oracle_check(q.r, q.state, q.steps, outs[q.rid].cpu().numpy())
     server.close()
+
+
+def test_native_server_device_memory_stays_under_the_cap():
+    """Requests of levels outside the reserved pool, in waves of shifting
+    levels: buffers the pool holds for one level must be freed before new
+    ones of another level would take the device bytes held past the cap."""
+    cap = 6 * footprint(10)
+    server = NativeServer(B.make_tune(64, 8, 0, 256), cap, 64)
+    server.reserve([10, 10, 10])  # pool of level 10 only
+    rng = np.random.default_rng(31)
+    waves = [[6, 7, 8, 9] * 3, [11], [9, 9, 10, 10, 8, 8], [11, 6, 7], [10] * 6]
+    rid = 0
+    for levels in waves:
+        reqs = []
+        for r in levels:
+            reqs.append(Request(rid, 0.0, r, int(rng.integers(1, 20)),
+                                inputs.bernoulli_state(r, 0.5, 900 + rid)))
+            rid += 1
+        note(f"native server cap: wave of levels {levels}")
+        inits = {q.rid: torch.from_numpy(q.state).cuda() for q in reqs}
+        outs = {q.rid: torch.zeros_like(inits[q.rid]) for q in reqs}
+        st = serve_native(server, reqs, inits, outs)
+        assert len(st.results) == len(reqs) and not any(x.rejected for x in st.results)
+        stats = server.stats()
+        assert stats["max_allocated_bytes"] <= cap, stats
+        assert stats["allocated_bytes"] <= cap
+        for q in reqs:
+            oracle_check(q.r, q.state, q.steps, outs[q.rid].cpu().numpy())
+    server.close()
+
+
+def test_python_executor_device_memory_stays_under_the_cap():
+    cap = 6 * footprint(10)
+    ex = GpuExecutor(B.make_tune(64, 8, 0, 256), capacity=32, cap_bytes=cap)
+    ex.reserve([10, 10, 10], cap)
+    rng = np.random.default_rng(37)
+    rid = 0
+    for levels in ([6, 7, 8, 9] * 3, [11], [9, 9, 10, 10, 8, 8], [11, 6, 7]):
+        reqs = []
+        for r in levels:
+            reqs.append(Request(rid, 0.0, r, int(rng.integers(1, 20)),
+                                inputs.bernoulli_state(r, 0.5, 950 + rid)))
+            rid += 1
+        note(f"python executor cap: wave of levels {levels}")
+        st = ContinuousBatcher(ex, cap_bytes=cap, steps_per_pass=8, keep_outputs=True).serve(reqs)
+        assert ex.max_allocated <= cap and ex.allocated <= cap
+        for res in st.results:
+            q = reqs[res.rid - reqs[0].rid]
+            oracle_check(q.r, q.state, q.steps, res.output)
+    ex.close()
