@@ -27,9 +27,10 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(build_oracle.LIB):
+    path = os.environ.get("SG_ORACLE_LIB") or build_oracle.LIB  # another build, e.g. sanitized
+    if path == build_oracle.LIB and not os.path.exists(path):
         build_oracle.build()
-    lib = ctypes.CDLL(build_oracle.LIB)
+    lib = ctypes.CDLL(path)
     sig = {
         "sgo_member": (_int, [_i64, _i64]),
         "sgo_member_paper": (_int, [_i64, _i64, _i64]),

@@ -58,13 +58,16 @@ def source_digest(names=None) -> str:
     return h.hexdigest()[:16]
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    """Compile every HIP source and link libsg.so; returns the library path."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, jobs: int = 8, extra_flags=(), lib: str = LIB,
+          build_dir: str = BUILD_DIR) -> str:
+    """Compile every HIP source and link libsg.so; returns the library path.
+    extra_flags, lib and build_dir serve other builds of the same sources
+    (the sanitized host-code build of the CPU tests)."""
+    os.makedirs(build_dir, exist_ok=True)
     objs, procs = [], []
     for src in sources():
-        obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
-        cmd = [HIPCC, *HIP_FLAGS, "-c", src, "-o", obj]
+        obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+        cmd = [HIPCC, *HIP_FLAGS, *extra_flags, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,
@@ -74,13 +77,13 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
             _wait(procs.pop(0))
     for p in procs:
         _wait(p)
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra_flags, "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 def _wait(item):

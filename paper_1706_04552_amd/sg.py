@@ -162,7 +162,9 @@ _lib = None
 
 
 def library_path() -> str:
-    return _build.LIB
+    """libsg.so in the package, or the build named by SG_LIB_PATH (another
+    build of the same sources, e.g. with the host code sanitized)."""
+    return os.environ.get("SG_LIB_PATH") or _build.LIB
 
 
 def load() -> ctypes.CDLL:
@@ -170,9 +172,10 @@ def load() -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_build.LIB):
+    path = library_path()
+    if path == _build.LIB and not os.path.exists(path):
         _build.build()
-    lib = ctypes.CDLL(_build.LIB)
+    lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGNATURES.items():
         f = getattr(lib, name)
         f.restype = res
