@@ -532,6 +532,9 @@ def main():
                     help="skip the one-launch-per-generation sweep")
     ap.add_argument("--skip-write", action="store_true",
                     help="skip the write-pass legs")
+    ap.add_argument("--skip-write-variants", action="store_true",
+                    help="time only the write pass itself (no intra-block, rectangular or "
+                         "paper-protocol legs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the sweep, diffusion, batched, fractal and serving legs")
@@ -658,7 +661,7 @@ def main():
                     torch, lambda: sg.sg_write_pass(map_kind, R, rho, Wt, 1), REPS, W, write_calls)
                 log(f"write {map_kind:6s} rho={rho:3d}: {med(wp[map_kind][rho]) * 1e3:9.2f} us")
         # the paper's other intra-block mappings (one thread per gasket cell)
-        for variant in ("unroll", "lut"):
+        for variant in (() if args.skip_write_variants else ("unroll", "lut")):
             for map_kind in ("lambda", "bbox"):
                 for rho in [x for x in args.rho if x <= 32]:
                     t = time_samples(torch, lambda: sg.sg_write_pass_intra(map_kind, variant, R, rho, Wt, 1),
@@ -666,7 +669,8 @@ def main():
                     intra.setdefault(variant, {}).setdefault(map_kind, {})[str(rho)] = us_stats(t)
                     log(f"write {variant:6s} {map_kind:6s} rho={rho:3d}: {med(t) * 1e3:9.2f} us")
         # rectangular blocks: whole 64-byte rows with fewer cells per block
-        for (rx, ry) in ((64, 4), (64, 16), (128, 8), (256, 4), (256, 16), (256, 64)):
+        for (rx, ry) in (() if args.skip_write_variants else
+                         ((64, 4), (64, 16), (128, 8), (256, 4), (256, 16), (256, 64))):
             for map_kind in ("lambda", "bbox"):
                 t = time_samples(torch, lambda: sg.sg_write_pass_rect(map_kind, R, rx, ry, Wt, 1),
                                  REPS, W, write_calls)
@@ -677,7 +681,7 @@ def main():
         # each the mean time of 10 consecutive calls, every call followed by a
         # device synchronisation; host clock, so launch and synchronisation
         # overhead are included.  Over the paper's block sides rho = 1..32.
-        for map_kind in ("lambda", "bbox"):
+        for map_kind in (() if args.skip_write_variants else ("lambda", "bbox")):
             for rho in (1, 2, 4, 8, 16, 32):
                 sg.sg_write_pass(map_kind, R, rho, Wt, 1)
                 torch.cuda.synchronize()
@@ -831,7 +835,7 @@ def main():
             "best_rho": {"lambda": wl, "bbox": wb},
             "intra_block_variants_us": intra,
             "rectangular_blocks_us": rect,
-            "paper_protocol": {
+            "paper_protocol": None if pl is None else {
                 "what": "mean of 100 sub-averages of 10 consecutive calls, each followed by a "
                         "device synchronisation (host clock: launch and sync overhead included)",
                 "us": paper, "best_rho": {"lambda": int(pl), "bbox": int(pb)},
