@@ -400,6 +400,24 @@ SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
 /* Waits for the context's last upload and frees it (NULL is ignored). */
 SG_API void sg_pass_ctx_destroy(sg_pass_ctx *ctx);
 
+/* For callers that cannot allocate (code under hipGraph capture, serving
+ * loops that must not call hipMalloc, harnesses that forbid it): the batched
+ * pass of sg_pass_run with no context.  The item table lives in a static
+ * device array of SG_PASS_STATIC_MAX items (32 bytes each, 128 KiB), one per
+ * GPU, held until the process ends; its device address is looked up on the
+ * first call on each device.  The items (host array, validated as by
+ * sg_pass_run) reach that table through the arguments of small staging
+ * launches on `stream`, so the host array may be reused as soon as the call
+ * returns.  No memory is allocated or freed, host or device.
+ * Every call on one GPU writes that GPU's one table: calls queued on the same
+ * stream run in order, but calls whose passes can overlap on the device (two
+ * streams, or two host threads) race, and the caller must order them.
+ * Results are identical to sg_pass_run's.
+ * Errors: SG_EINVAL (count > SG_PASS_STATIC_MAX, or as sg_pass_run),
+ * SG_EALIAS, SG_EHIP. */
+#define SG_PASS_STATIC_MAX 4096
+SG_API int sg_pass_run_static(const sg_pass_item *items, int count, const sg_tune *tune,
+                              void *stream);
 
 /* ---------------------------------------------------------------------
  * Continuous batching of life solves (a native serving loop over

@@ -110,6 +110,20 @@ PASS_ITEM = np.dtype([("src", np.uint64), ("dst", np.uint64), ("r", np.int32),
 assert PASS_ITEM.itemsize == ctypes.sizeof(sg.sg_pass_item)
 
 
+def run_static(items: List[tuple], tune, stream=None):
+    """One batched pass with no context and no allocation
+    (sg_pass_run_static): items (src, dst, r, steps) with src/dst uint8
+    device tensors, at most SG_PASS_STATIC_MAX of them."""
+    arr = (sg.sg_pass_item * max(1, len(items)))()
+    for i, (src, dst, r, steps) in enumerate(items):
+        arr[i].src = _ptr(src, r, "src")
+        arr[i].dst = _ptr(dst, r, "dst")
+        arr[i].r = r
+        arr[i].steps = steps
+    sg._check(sg.load().sg_pass_run_static(arr, len(items), ctypes.byref(tune),
+                                           sg._stream(stream)), "sg_pass_run_static")
+
+
 class PassContext:
     """Device item table for repeated batched passes over a changing set of
     gaskets (continuous batching)."""

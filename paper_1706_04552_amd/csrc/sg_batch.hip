@@ -423,6 +423,103 @@ SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
   });
 }
 
+}  // extern "C"
+
+// The item table of the allocation-free pass (sg_pass_run_static): one per
+// GPU, in the code object's device memory, held until the process ends.
+static __device__ __align__(256) sg::BatchItem scratch[SG_PASS_STATIC_MAX];
+
+namespace {
+
+// Items reach the table through kernel arguments, a chunk per launch: the
+// runtime copies a launch's arguments when the launch is queued, so no host
+// buffer has to outlive the call, and nothing is allocated.
+constexpr int kStageChunk = 64;  // 64 items of 32 bytes: 2 KiB of arguments
+struct StageChunk {
+  sg::BatchItem items[kStageChunk];
+};
+
+__global__ __launch_bounds__(kStageChunk) void k_stage_items(StageChunk chunk, int count,
+                                                             sg::BatchItem *table) {
+  const int i = (int)threadIdx.x;
+  if (i < count) table[i] = chunk.items[i];
+}
+
+// The device address of `scratch` on each device, looked up once per device
+// (with that device current) by hipGetSymbolAddress.  Host code uses only
+// these addresses: the array's own name is a host-side stand-in.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+sg::BatchItem *g_scratch[kMaxDevices] = {};
+
+int scratch_table(sg::BatchItem **out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return SG_EHIP;
+  if (dev < 0 || dev >= kMaxDevices) return SG_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SG_EHIP;
+    g_scratch[dev] = static_cast<sg::BatchItem *>(p);
+  }
+  *out = g_scratch[dev];
+  return SG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+SG_API int sg_pass_run_static(const sg_pass_item *items, int count, const sg_tune *tune,
+                              void *stream) {
+  if (count < 0 || count > SG_PASS_STATIC_MAX || (count > 0 && !items)) return SG_EINVAL;
+  int st = check_tune(tune);
+  if (st != SG_OK) return st;
+  // validate everything before touching the device (as sg_pass_run)
+  int live = 0, max_steps = 0;
+  for (int i = 0; i < count; ++i) {
+    const sg_pass_item &it = items[i];
+    if (it.steps < 0 || it.steps > tune->steps_per_pass) return SG_EINVAL;
+    if (it.steps == 0) continue;
+    if (it.r < kMinTileLog2 || it.r > SG_MAX_R || !it.src || !it.dst) return SG_EINVAL;
+    if (misaligned(it.src) || misaligned(it.dst)) return SG_EINVAL;
+    if (overlaps(it.src, it.dst, ((size_t)1 << it.r) * ((size_t)1 << it.r))) return SG_EALIAS;
+    ++live;
+    max_steps = std::max(max_steps, (int)it.steps);
+  }
+  if (live == 0) return SG_OK;
+  if (sg::inject_hip_error()) return SG_EHIP;
+  sg::BatchItem *table = nullptr;
+  st = scratch_table(&table);
+  if (st != SG_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const int kmax = rho_log2(tune->rho);
+  StageChunk chunk;
+  uint64_t tiles = 0;
+  int m = 0, c = 0;
+  for (int i = 0; i < count; ++i) {
+    const sg_pass_item &it = items[i];
+    if (it.steps == 0) continue;
+    sg::BatchItem &b = chunk.items[c++];
+    b.src = it.src;
+    b.dst = it.dst;
+    b.r = it.r;
+    b.steps = (int16_t)it.steps;
+    b.k = (int16_t)item_k(it.r, kmax);
+    b.tile_begin = tiles;
+    tiles += pow3(it.r - b.k);
+    if (c == kStageChunk || m + c == live) {
+      hipLaunchKernelGGL(k_stage_items, dim3(1), dim3(kStageChunk), 0, s, chunk, c, table + m);
+      st = hip_err(hipGetLastError());
+      if (st != SG_OK) return st;
+      m += c;
+      c = 0;
+    }
+  }
+  return hip_err(sg::launch_life_tb_batch(tune->rho, tune->threads, table, m, tiles, max_steps,
+                                          groups_for(*tune, tiles), s));
+}
+
 SG_API void sg_pass_ctx_destroy(sg_pass_ctx *ctx) {
   if (!ctx) return;
   for (int k = 0; k < kPassRing; ++k) {

@@ -19,6 +19,7 @@ SG_MAP_LAMBDA, SG_MAP_BBOX = 0, 1
 SG_INTRA_SUBBOX, SG_INTRA_UNROLL, SG_INTRA_LUT = 0, 1, 2
 INTRA = {"subbox": SG_INTRA_SUBBOX, "unroll": SG_INTRA_UNROLL, "lut": SG_INTRA_LUT}
 SG_MAX_R, SG_MAX_RHO = 20, 256
+SG_PASS_STATIC_MAX = 4096  # items of sg_pass_run_static
 MAPS = {"lambda": SG_MAP_LAMBDA, "bbox": SG_MAP_BBOX}
 
 class sg_tune(ctypes.Structure):
@@ -145,6 +146,7 @@ _SIGNATURES = {
     "sg_pass_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_vp)]),
     "sg_pass_run": (ctypes.c_int, [_vp, ctypes.POINTER(sg_pass_item), ctypes.c_int, _tunep, _vp]),
     "sg_pass_ctx_destroy": (None, [_vp]),
+    "sg_pass_run_static": (ctypes.c_int, [ctypes.POINTER(sg_pass_item), ctypes.c_int, _tunep, _vp]),
 }
 
 
