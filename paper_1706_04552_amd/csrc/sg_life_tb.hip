@@ -73,10 +73,15 @@ __device__ __forceinline__ int div_small(int e, uint32_t m) {
   return (int)(__umul24((uint32_t)e, m) >> 20);
 }
 
-// 16 bytes holding 0/1 -> 16 bits (bit i = byte i).
+// 16 bytes holding 0/1 -> 16 bits (bit i = byte i): each 4-byte word is a
+// dot product of its bytes with the weights 1, 2, 4, 8 (or 16..128 for the
+// upper nibble of a byte), one v_dot4_u32_u8 each, accumulated in pairs.
 __device__ __forceinline__ uint32_t pack16(const uint4 v) {
-  auto p4 = [](uint32_t w) { return (w | (w >> 7) | (w >> 14) | (w >> 21)) & 0xFu; };
-  return p4(v.x) | (p4(v.y) << 4) | (p4(v.z) << 8) | (p4(v.w) << 12);
+  const uint32_t lo = __builtin_amdgcn_udot4(
+      v.y, 0x80402010u, __builtin_amdgcn_udot4(v.x, 0x08040201u, 0u, false), false);
+  const uint32_t hi = __builtin_amdgcn_udot4(
+      v.w, 0x80402010u, __builtin_amdgcn_udot4(v.z, 0x08040201u, 0u, false), false);
+  return lo | (hi << 8);
 }
 
 // 16 bits -> 16 bytes holding 0/1.
@@ -141,6 +146,74 @@ __device__ __forceinline__ uint32_t life_rule(const RowSums &u, const RowSums &m
   return bop3<kA & (kB | kC)>(f, s0, m.self) & mask;                          // f & (s0 | self)
 }
 
+// Work units of a tile pass's region load and store, fixed per tile side.
+//
+// Inside any block of the gasket's block grid that holds gasket cells, the
+// 16-byte chunk c (cells 16c..16c+15 of a row) of the 16-row band q (rows
+// 16q..16q+15) holds gasket cells iff (c & q) == 0, in every row of the
+// band: x & y = (block bits) | (16c & y) | (lower bits), and 16c & y only
+// sees bits 4.. of the row.  A load unit is 64 lanes: 16 rows of one band of
+// one of the 3 x 3 blocks around the tile times 4 slots, each slot a live
+// (band, chunk) pair of that block inside the pass's region (the tile, its
+// halo rows of up to 32 above and below, its halo word each side); so only
+// chunks that hold gasket cells are loaded and packed.  A store unit is a
+// 64-byte granule g (4 chunks) of a tile band q, live iff (g & (q >> 2)) == 0,
+// as 16 rows x 4 chunks.  Whether a neighbour block holds gasket cells, and
+// which halo rows a pass of T generations needs, are decided when the pass
+// runs.
+constexpr int kMaxUnits = 64;
+constexpr uint32_t kNoPair = 0xFFu;  // an empty slot (band 15, chunk 15: never live)
+
+struct TileUnits {
+  int nload = 0, nstore = 0;
+  uint32_t load_pairs[kMaxUnits] = {};  // 4 slots of 8 bits: band << 4 | chunk
+  uint32_t load_block[kMaxUnits] = {};  // (dbx + 1) + 3 (dby + 1)
+  uint32_t store_pairs[kMaxUnits] = {}; // band << 4 | granule
+};
+
+template <int RHO>
+constexpr TileUnits make_tile_units() {
+  TileUnits t{};
+  constexpr int NC = RHO / 16;  // chunk columns and bands per block
+  // the tile first, then the halo blocks
+  const int order[9][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1},
+                           {-1, -1}, {1, -1}, {-1, 1}, {1, 1}};
+  for (const auto &o : order) {
+    const int dbx = o[0], dby = o[1];
+    const int q0 = dby < 0 ? NC - 2 : 0, q1 = dby > 0 ? 2 : NC;  // the region's bands
+    const int c0 = dbx < 0 ? NC - 2 : 0, c1 = dbx > 0 ? 2 : NC;  // and chunk columns
+    int slot = 0;
+    uint32_t word = 0;
+    for (int q = q0; q < q1; ++q)
+      for (int c = c0; c < c1; ++c) {
+        if ((q & c) != 0) continue;
+        word |= (uint32_t)((q << 4) | c) << (8 * slot);
+        if (++slot == 4) {
+          t.load_pairs[t.nload] = word;
+          t.load_block[t.nload++] = (uint32_t)((dbx + 1) + 3 * (dby + 1));
+          slot = 0;
+          word = 0;
+        }
+      }
+    if (slot) {
+      for (; slot < 4; ++slot) word |= kNoPair << (8 * slot);
+      t.load_pairs[t.nload] = word;
+      t.load_block[t.nload++] = (uint32_t)((dbx + 1) + 3 * (dby + 1));
+    }
+  }
+  for (int q = 0; q < NC; ++q)
+    for (int g = 0; g < RHO / 64; ++g)
+      if ((g & (q >> 2)) == 0) t.store_pairs[t.nstore++] = (uint32_t)((q << 4) | g);
+  return t;
+}
+
+template <int RHO>
+struct TileUnitTable {
+  static constexpr TileUnits units = make_tile_units<RHO>();
+};
+template <int RHO>
+__constant__ TileUnits kTileUnits = TileUnitTable<RHO>::units;
+
 // Where a tile pass reads and writes cells.
 //
 // DenseMem: the 2^lgn x 2^lgn embedding itself (row y at y << lgn; callers
@@ -188,13 +261,78 @@ struct CompactMem {
   __device__ __forceinline__ uint8_t *dst(int y, int x) const { return out + tile_off(y, x); }
 };
 
+// The region loads of one tile pass, in flight in registers until packed:
+// wave w holds the loads of load units w, w + NW, ... (TileUnits).
+template <int RHO, int NT>
+struct RegionLoads {
+  static constexpr int NW = NT / 64;                            // waves per workgroup
+  static constexpr int NU = TileUnitTable<RHO>::units.nload;   // load units
+  static constexpr int UPW = (NU + NW - 1) / NW;               // load units per wave
+  uint4 v[UPW];
+  uint32_t live;  // bit k: this lane's slot of unit w + k NW was loaded
+};
+
+// Issues the region loads of the tile at block (bx, by) for a pass of T
+// generations.  A unit whose block holds no gasket cell (or lies off the
+// grid) is skipped by the whole wave; in the others, a lane loads its chunk
+// if that chunk lies in the region (the tile, T rows above and below, and
+// the halo chunks within T cells of it).  Nothing waits for the loads here.
+template <int RHO, int NT, class Mem>
+__device__ __forceinline__ void tb_load(const Mem &mem, int r, uint32_t bx, uint32_t by, int T,
+                                        RegionLoads<RHO, NT> &ld) {
+  using LD = RegionLoads<RHO, NT>;
+  constexpr int NC = RHO / 16;      // chunk columns (and bands) per block
+  constexpr int CH = RHO / 16 + 4;  // 16-byte chunks per region row
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  const int lane = __lane_id();
+  const int nbk = 1 << (r - rho_log2_const(RHO));  // blocks per grid side
+  const int R = RHO + 2 * T, jlo = T > 16 ? 0 : 1;
+  const int yr0 = (int)by * RHO - T;  // row of region row 0
+  ld.live = 0u;
+#pragma unroll
+  for (int k = 0; k < LD::UPW; ++k) {
+    const int u = wave + k * LD::NW;
+    bool ok = false;
+    int y = 0, x = 0;
+    if (u < LD::NU) {
+      const uint32_t blk = kTileUnits<RHO>.load_block[u];
+      const int dbx = (int)(blk % 3u) - 1, dby = (int)(blk / 3u) - 1;
+      const int Bx = (int)bx + dbx, By = (int)by + dby;
+      if (Bx >= 0 && By >= 0 && Bx < nbk && By < nbk && (Bx & By) == 0) {
+        const uint32_t pr = (kTileUnits<RHO>.load_pairs[u] >> (8 * (lane & 3))) & 0xFFu;
+        const int q = (int)(pr >> 4), c = (int)(pr & 15u);
+        y = By * RHO + 16 * q + (lane >> 2);
+        x = Bx * RHO + 16 * c;
+        const int i = y - yr0;            // region row
+        const int jr = dbx * NC + c + 2;  // region chunk column
+        ok = pr != kNoPair && (unsigned)i < (unsigned)R && jr >= jlo && jr < CH - jlo;
+      }
+    }
+    // a defined value either way keeps each load in its own registers, so
+    // the wave's loads stay in flight together
+    ld.v[k] = ok ? *reinterpret_cast<const uint4 *>(mem.src(y, x)) : make_uint4(0u, 0u, 0u, 0u);
+    ld.live |= (ok ? 1u : 0u) << k;
+  }
+}
+
+// A 16-byte store of a pass's output.  Streaming (non-temporal): nothing
+// reads the output within the pass, and keeping it out of the caches leaves
+// them to the region reads, whose halos neighbouring tiles share.
+__device__ __forceinline__ void store16_stream(uint8_t *p, const uint4 w) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 v = {w.x, w.y, w.z, w.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+}
+
 // One tile pass: the rho x rho tile at block (bx, by) of the gasket of level
-// r advanced by T generations from mem.src to mem.dst, by NT threads.  `lds`
-// holds tb_lds_bytes<RHO>(T) bytes (or more); the caller synchronises the
-// workgroup before reusing it.
+// r advanced by T generations from mem.src to mem.dst, by NT threads, from
+// its region loads `ld` (issued by tb_load; a compact Mem is prepared).
+// `lds` holds tb_lds_bytes<RHO>(T) bytes (or more); the caller synchronises
+// the workgroup before reusing it.
 template <int RHO, int NT, class Mem>
 __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint32_t by, int T,
-                                        uint32_t *lds, uint32_t *nseg_p) {
+                                        uint32_t *lds, uint32_t *nseg_p,
+                                        const RegionLoads<RHO, NT> &ld) {
   uint32_t &nseg = *nseg_p;
   constexpr int kTbThreads = NT;
   // Region columns [X0-32, X0+RHO+32): the tile plus one 32-cell word each
@@ -216,9 +354,8 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   const int RP = NB * L;              // region rows rounded up to whole blocks
   const int PR = RP + 2;              // plane rows (zero guard row above, below)
   const int tid = threadIdx.x;
-  // chunks [jlo, jlo + CHL) of a region row lie within T cells of the tile
+  // chunks [jlo, CH - jlo) of a region row lie within T cells of the tile
   const int jlo = T > 16 ? 0 : 1;
-  const int CHL = CH - 2 * jlo;
 
   // n <= 2^20, so cell coordinates (halo included) fit in 32-bit ints
   const int n = 1 << r;
@@ -230,8 +367,14 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   uint32_t *rowpat = plane1 + PR * PW;  // RP: gasket pattern of each region row
   uint32_t *segs = rowpat + RP;         // W * NB: listed segments
 
-  mem.prepare(tid, bx, by, r - rho_log2_const(RHO));
-  for (int i = tid; i < 2 * PR * PW; i += kTbThreads) lds[i] = 0u;
+  {
+    // both planes cleared, 16 bytes per store (the region loads are in flight)
+    constexpr int kAlign = 4;
+    const int words = 2 * PR * PW, n4 = words / kAlign;
+    uint4 *z = reinterpret_cast<uint4 *>(lds);
+    for (int i = tid; i < n4; i += kTbThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
+    for (int i = kAlign * n4 + tid; i < words; i += kTbThreads) lds[i] = 0u;
+  }
   for (int i = tid; i < RP; i += kTbThreads) {
     const int y = yr0 + i;
     rowpat[i] = (i < R && y >= 0 && y < n) ? word_pattern((uint32_t)y) : 0u;
@@ -239,32 +382,26 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   if (tid == 0) nseg = 0u;
   __syncthreads();
 
-  // 1. load and bit-pack the region, kLoadBatch loads in flight per thread.
-  //    Thread tid takes chunk column jlo + tid % CHL of region rows tid / CHL,
-  //    tid / CHL + RPB, ... (RPB = kTbThreads / CHL rows per round), so the
-  //    column's part of every address is found once.
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
+  const int lane = __lane_id();
+  constexpr int NW = kTbThreads / 64;  // waves per workgroup
+
+  // 1. bit-pack the region loads into plane 0 (each load unit's chunk goes
+  //    to its region row and chunk column).
   uint16_t *p0h = reinterpret_cast<uint16_t *>(plane0);
   {
-    const int RPB = kTbThreads / CHL;
-    const int ti = tid / CHL, j = jlo + (tid - ti * CHL);
-    const int x = X0 - 32 + 16 * j;
-    const int slot0 = (PW + (j >> 1) + 1) * 2 + (j & 1);  // region row 0 at plane row 1
-    if (ti < RPB && x >= 0 && x < n) {
-      for (int i0 = ti; i0 < R; i0 += RPB * kLoadBatch) {
-        uint4 v[kLoadBatch];
-        bool ok[kLoadBatch];
+    using LD = RegionLoads<RHO, NT>;
+    constexpr int NC = RHO / 16;
 #pragma unroll
-        for (int q = 0; q < kLoadBatch; ++q) {
-          const int i = i0 + q * RPB, y = yr0 + i;
-          ok[q] = i < R && (uint32_t)y < (uint32_t)n && (x & y) == 0;
-          // a defined value either way keeps each load in its own registers,
-          // so the batch's loads stay in flight together
-          v[q] = ok[q] ? *reinterpret_cast<const uint4 *>(mem.src(y, x)) : make_uint4(0u, 0u, 0u, 0u);
-        }
-#pragma unroll
-        for (int q = 0; q < kLoadBatch; ++q)
-          if (ok[q]) p0h[slot0 + (i0 + q * RPB) * (2 * PW)] = (uint16_t)pack16(v[q]);
-      }
+    for (int k = 0; k < LD::UPW; ++k) {
+      if (!((ld.live >> k) & 1u)) continue;
+      const int u = wave + k * LD::NW;
+      const uint32_t blk = kTileUnits<RHO>.load_block[u];
+      const int dbx = (int)(blk % 3u) - 1, dby = (int)(blk / 3u) - 1;
+      const uint32_t pr = (kTileUnits<RHO>.load_pairs[u] >> (8 * (lane & 3))) & 0xFFu;
+      const int i = dby * RHO + 16 * (int)(pr >> 4) + (lane >> 2) + T;  // region row
+      const int jr = dbx * NC + (int)(pr & 15u) + 2;                    // region chunk column
+      p0h[((i + 1) * PW + (jr >> 1) + 1) * 2 + (jr & 1)] = (uint16_t)pack16(ld.v[k]);
     }
   }
 
@@ -272,7 +409,6 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   //    hold a gasket cell, listed column by column; each entry keeps the rows
   //    whose word starts on the gasket (then its cells are exactly those of
   //    the row's pattern)
-  const int lane = __lane_id();
   const uint32_t nb_magic = div_small_magic((uint32_t)NB);
   for (int base = 0; base < W * NB; base += kTbThreads) {
     const int e = base + tid;
@@ -361,45 +497,70 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   }
   const uint16_t *fin = reinterpret_cast<const uint16_t *>((T & 1) ? plane1 : plane0);
 
-  // 4. unpack and store the tile, whole granules (64 bytes, or a 32-byte row).
-  //    Thread tid takes chunk column tid % TC of tile rows tid / TC, + RPS, ...
-  constexpr int TC = RHO / 16;          // 16-byte chunks per tile row
-  constexpr int RPS = kTbThreads / TC;  // tile rows per round
-  static_assert(kTbThreads % TC == 0, "the store rounds cover whole rows");
-  {
+  // 4. unpack and store the tile.  In the embedding, a wave takes the store
+  //    units w, w + NW, ... (TileUnits): 16 rows of one 64-byte granule that
+  //    holds gasket cells, so every granule written is written whole and
+  //    granules without a gasket cell are never touched.  A compact tile, and
+  //    the 32-byte rows of rho = 32, are rewritten whole: thread tid takes
+  //    chunk column tid % TC of tile rows tid / TC, + RPS, ...
+  constexpr int TC = RHO / 16;  // 16-byte chunks per tile row
+  if constexpr (!Mem::kCompact && RHO >= 64) {
+    constexpr int NS = TileUnitTable<RHO>::units.nstore;
+    for (int u = wave; u < NS; u += NW) {
+      const uint32_t pr = kTileUnits<RHO>.store_pairs[u];
+      const int ty = 16 * (int)(pr >> 4) + (lane >> 2);
+      const int j = 4 * (int)(pr & 15u) + (lane & 3);  // tile chunk; region chunk j + 2
+      const uint32_t bits = fin[((T + 1 + ty) * PW + 2 + (j >> 1)) * 2 + (j & 1)];
+      store16_stream(mem.dst(Y0 + ty, X0 + 16 * j), unpack16(bits));
+    }
+  } else {
+    constexpr int RPS = kTbThreads / TC;  // tile rows per round
+    static_assert(kTbThreads % TC == 0, "the store rounds cover whole rows");
     const int j = tid % TC, x = X0 + 16 * j;
-    const int w = 1 + (j >> 1), half = j & 1;  // region chunk j + 2
-    const int f0 = ((T + 1) * PW + (w + 1)) * 2 + half;
+    const int f0 = ((T + 1) * PW + 2 + (j >> 1)) * 2 + (j & 1);
     for (int ty = tid / TC; ty < RHO; ty += RPS) {
       const int y = Y0 + ty;
-      // the embedding keeps granules without a gasket cell untouched; a
-      // compact tile is rewritten whole
+      // the embedding keeps rows without a gasket cell untouched (none at
+      // rho = 32: every row of a gasket block holds its cell 0)
       if (!Mem::kCompact && ((x & ~(G - 1)) & y) != 0) continue;
       const uint32_t bits = fin[f0 + ty * (2 * PW)];
-      *reinterpret_cast<uint4 *>(mem.dst(y, x)) = unpack16(bits);
+      store16_stream(mem.dst(y, x), unpack16(bits));
     }
   }
 }
 
-// One workgroup per tile of one gasket.
+// Block (bx, by) of tile t of a pass over the lambda map's 3^rb tiles, or
+// the bounding box's 4^rb; false for a bounding-box tile off the gasket.
+template <bool LAMBDA>
+__device__ __forceinline__ bool tile_block(uint64_t t, int rb, uint32_t &bx, uint32_t &by) {
+  if constexpr (LAMBDA) {
+    pass_decode((uint32_t)t, rb, bx, by);
+    return true;
+  } else {
+    by = (uint32_t)(t >> rb);
+    bx = (uint32_t)(t & ((1ull << rb) - 1ull));
+    return (bx & by) == 0u;
+  }
+}
+
+// One workgroup per tile of one gasket.  Its region loads are issued first,
+// so they are in flight while the LDS planes are cleared.
 template <int RHO, bool LAMBDA>
 __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__restrict__ in,
                                                                uint8_t *__restrict__ out, int r,
                                                                int rb, uint64_t tile_base,
                                                                uint64_t ntiles, int T) {
-  extern __shared__ uint32_t lds[];
+  constexpr int NT = tb_threads<RHO>();
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t nseg;
   const uint64_t t = tile_base + logical_group();
   if (t >= ntiles) return;
   uint32_t bx, by;
-  if constexpr (LAMBDA) {
-    pass_decode((uint32_t)t, rb, bx, by);
-  } else {
-    by = (uint32_t)(t >> rb);
-    bx = (uint32_t)(t & ((1ull << rb) - 1ull));
-    if ((bx & by) != 0u) return;
-  }
-  tb_tile<RHO, tb_threads<RHO>()>(DenseMem{in, out, r}, r, bx, by, T, lds, &nseg);
+  if (!tile_block<LAMBDA>(t, rb, bx, by)) return;
+  const DenseMem mem{in, out, r};
+  RegionLoads<RHO, NT> ld;
+  tb_load<RHO, NT>(mem, r, bx, by, T, ld);
+  tb_tile<RHO, NT>(mem, r, bx, by, T, lds, &nseg, ld);
 }
 
 // One workgroup per tile of a gasket in block-compacted storage (lambda
@@ -408,7 +569,7 @@ template <int RHO>
 __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb_compact(
     const uint8_t *__restrict__ in, uint8_t *__restrict__ out, int r, int rb,
     uint64_t tile_base, uint64_t ntiles, int T) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t nseg;
   __shared__ int32_t nbr[9];
   const uint64_t t = tile_base + logical_group();
@@ -416,7 +577,20 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb_compact(
   uint32_t bx, by;
   lambda_decode((uint32_t)t, rb, bx, by);  // storage order
   const CompactMem<RHO> mem{in, out, nbr, (int)bx, (int)by};
-  tb_tile<RHO, tb_threads<RHO>()>(mem, r, bx, by, T, lds, &nseg);
+  mem.prepare((int)threadIdx.x, bx, by, rb);
+  __syncthreads();  // the neighbour tiles' omegas
+  RegionLoads<RHO, tb_threads<RHO>()> ld;
+  tb_load<RHO, tb_threads<RHO>()>(mem, r, bx, by, T, ld);
+  tb_tile<RHO, tb_threads<RHO>()>(mem, r, bx, by, T, lds, &nseg, ld);
+}
+
+// One tile of a batched pass: its region loads, then the tile pass.
+template <int RHO, int NT>
+__device__ __forceinline__ void batch_tile(const DenseMem &mem, int r, uint32_t bx, uint32_t by,
+                                           int T, uint32_t *lds, uint32_t *nseg) {
+  RegionLoads<RHO, NT> ld;
+  tb_load<RHO, NT>(mem, r, bx, by, T, ld);
+  tb_tile<RHO, NT>(mem, r, bx, by, T, lds, nseg, ld);
 }
 
 // Many gaskets in one persistent launch: workgroups stride over the global
@@ -428,7 +602,7 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb_compact(
 template <int MAXRHO, int NT>
 __global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restrict__ items,
                                                       int count, uint64_t total_tiles) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t nseg;
   for (uint64_t g = blockIdx.x; g < total_tiles; g += gridDim.x) {
     int lo = 0, hi = count - 1;
@@ -439,14 +613,13 @@ __global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restric
     const BatchItem it = items[lo];
     uint32_t bx, by;
     pass_decode((uint32_t)(g - it.tile_begin), it.r - it.k, bx, by);
+    const DenseMem mem{it.src, it.dst, it.r};
     if (it.k == 6) {
-      tb_tile<64, NT>(DenseMem{it.src, it.dst, it.r}, it.r, bx, by, it.steps, lds, &nseg);
+      batch_tile<64, NT>(mem, it.r, bx, by, it.steps, lds, &nseg);
     } else if (MAXRHO >= 128 && it.k == 7) {
-      tb_tile<(MAXRHO >= 128 ? 128 : 64), NT>(DenseMem{it.src, it.dst, it.r}, it.r, bx, by,
-                                              it.steps, lds, &nseg);
+      batch_tile<(MAXRHO >= 128 ? 128 : 64), NT>(mem, it.r, bx, by, it.steps, lds, &nseg);
     } else if (MAXRHO >= 256 && it.k == 8) {
-      tb_tile<(MAXRHO >= 256 ? 256 : 64), NT>(DenseMem{it.src, it.dst, it.r}, it.r, bx, by,
-                                              it.steps, lds, &nseg);
+      batch_tile<(MAXRHO >= 256 ? 256 : 64), NT>(mem, it.r, bx, by, it.steps, lds, &nseg);
     }
     __syncthreads();  // the next tile reuses the LDS planes
   }

@@ -1,7 +1,7 @@
 """Code-generation guards for the temporally blocked passes (no GPU needed).
 
-The tile pass keeps a batch of region loads in flight per thread before it
-bit-packs any of them.  If the compiler moves work that uses a loaded value
+The tile pass keeps a batch of region loads in flight per thread (one per
+load unit of its wave) before it bit-packs any of them.  If the compiler moves work that uses a loaded value
 into the load's own conditional block, it has to wait for that load there
 (`s_waitcnt vmcnt(0)` right after it) and the batch is serialised, which cost
 8 % of the pass at rho = 256 when it happened.  These tests compile the passes
@@ -59,7 +59,7 @@ def test_tile_pass_region_loads_stay_in_flight(asm):
     assert len(kernels) >= 8  # dense (both maps, four sides), compact and batch variants
     for name, lines in kernels:
         loads = sum(1 for l in lines if re.match(r"(global|flat)_load_dwordx4\b", l))
-        assert loads >= 4, name  # the batch of region loads
+        assert loads >= 2, name  # a wave's batch of region loads (one per load unit)
         assert _waited_at_once(lines) == 0, name
 
 
