@@ -411,80 +411,71 @@ def bench_fractals(torch, sg, r, steps):
 
 def bench_serving(torch, sg, inputs, qps_list, count, cap_gb, horizon_cells=None,
                   budget_cells=None):
-    """Poisson arrivals of life solves (r ~ U{8..15}, steps ~ U{10..200}) served
-    by continuous batching under an HBM footprint cap, against one request at
-    a time on the same arrivals (FIFO, each request's measured service time
-    alone, including the copy of its initial state into device buffers).
+    """Poisson arrivals of life solves (r ~ U{8..15}, steps ~ U{10..200})
+    served by the native continuous-batching server (sg_server_replay: the
+    arrivals, admission by HBM footprint under the cap, the rounds of batched
+    passes and the latency clock are all in native code), against the same
+    loop admitting one request at a time (max_active = 1) on the same
+    arrivals.  In host mode the server starts a request's upload only while
+    no other host transfer is in flight (its default transfer window of 1);
+    the same run without that window is reported too.  Two input modes:
+      host: each request's initial state is uploaded from pinned host memory
+        when it is admitted and its result read back into pinned host memory
+        when it finishes (copy streams beside the passes); a request's
+        latency ends when its read-back has completed;
+      resident: initial states already on the device, results left there.
     Requests of one level share an initial state (Bernoulli(0.5), seed
-    1706 + r); the passes' cost does not depend on it."""
+    1706 + r) and, in host mode, one pinned result buffer: the passes' and
+    transfers' costs do not depend on the contents."""
     from paper_1706_04552_amd import batch, serving
-    templates = {r: torch.from_numpy(inputs.bernoulli_state(r, 0.5, SEED + r)).cuda()
-                 for r in range(8, 16)}
+    levels = range(8, 16)
+    dev_t = {r: torch.from_numpy(inputs.bernoulli_state(r, 0.5, SEED + r)).cuda() for r in levels}
+    host_t = {r: dev_t[r].cpu().pin_memory() for r in levels}
+    host_o = {r: torch.empty_like(host_t[r]).pin_memory() for r in levels}
     # launch shape: autotuned once on a sample of the request mix
     sample = inputs.poisson_requests(1.0, 48, seed=SEED + 7)
-    gs = [batch.Gasket(q.r, q.steps, templates[q.r], torch.zeros_like(templates[q.r]),
-                       torch.zeros_like(templates[q.r])) for q in sample]
+    gs = [batch.Gasket(q.r, q.steps, dev_t[q.r], torch.zeros_like(dev_t[q.r]),
+                       torch.zeros_like(dev_t[q.r])) for q in sample]
     tune, _ = batch.autotune(gs)
     del gs
     torch.cuda.empty_cache()
+    cap = int(cap_gb * 1e9)
+    server = serving.NativeServer(tune, cap, count, int(horizon_cells or 0), int(budget_cells or 0))
+    first = inputs.poisson_requests(qps_list[0], count)
+    server.reserve([q.r for q in first])  # the server's pool, sized at start
     results = []
     for qps in qps_list:
         reqs = inputs.poisson_requests(qps, count)
-        rq = [serving.Request(q.rid, q.arrival, q.r, q.steps, template=q.r) for q in reqs]
-        ex = serving.GpuExecutor(tune, capacity=count, templates=templates)
-        ex.reserve([q.r for q in rq], int(cap_gb * 1e9))  # the server's memory pool
-        server = serving.ContinuousBatcher(ex, cap_bytes=int(cap_gb * 1e9),
-                                           steps_per_pass=tune.steps_per_pass,
-                                           horizon_cells=horizon_cells,
-                                           max_cells_per_pass=budget_cells)
-        server.serve(rq[:16])  # warm-up (first-call costs)
-        stats = server.serve(rq)
-        summ = stats.summary()
-        # one request at a time: each request alone (state copy + its steps)
-        svc = []
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        for q in rq:
-            h = ex.admit(q)  # pooled buffers, as the server uses
-            work = ex._buffer(q.r)
-            torch.cuda.synchronize()
-            e0.record()
-            h["buf"][0].copy_(templates[q.r])
-            sg.sg_ca_steps("lambda", q.r, tune.rho, q.steps, templates[q.r], h["buf"][1], work,
-                           steps_per_pass=tune.steps_per_pass)
-            e1.record()
-            torch.cuda.synchronize()
-            svc.append(e0.elapsed_time(e1) * 1e-3)
-            ex.release(h)
-            ex.pool[q.r].append(work)
-        ex.close()
-        del ex
-        torch.cuda.empty_cache()
-        # the same policy in native code (sg_server_*): queue, pool and rounds
-        nat = serving.NativeServer(tune, int(cap_gb * 1e9), count, int(horizon_cells or 0),
-                                   int(budget_cells or 0))
-        nat.reserve([q.r for q in rq])
-        inits = {q.rid: templates[q.r] for q in rq}
-        serving.serve_native(nat, rq[:16], inits)  # warm-up
-        nsumm = serving.serve_native(nat, rq, inits).summary()
-        nat.close()
-        del nat
-        torch.cuda.empty_cache()
-        summ["native_server"] = nsumm
-        lat, end = serving.sequential_baseline(svc, [q.arrival for q in rq])
+        rq = [serving.Request(q.rid, q.arrival, q.r, q.steps) for q in reqs]
         cells = float(sum(3 ** q.r * q.steps for q in rq))
-        summ["one_at_a_time"] = {"p50_ms": float(np.percentile(lat, 50) * 1e3),
-                                 "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                                 "cells_per_s": cells / end, "gpu_busy_s": float(sum(svc))}
-        summ.update({"qps": qps, "cap_gb": cap_gb})
-        log(f"serving qps={qps:.0f}: p50 {summ['p50_ms']:.2f} ms p99 {summ['p99_ms']:.2f} ms "
-            f"{summ['cells_per_s'] / 1e9:.1f} Gcells/s; one at a time p50 "
-            f"{summ['one_at_a_time']['p50_ms']:.2f} p99 {summ['one_at_a_time']['p99_ms']:.2f} ms "
-            f"{summ['one_at_a_time']['cells_per_s'] / 1e9:.1f} Gcells/s; native server p50 "
-            f"{nsumm['p50_ms']:.2f} p99 {nsumm['p99_ms']:.2f} ms "
-            f"{nsumm['cells_per_s'] / 1e9:.1f} Gcells/s")
-        results.append(summ)
+        row = {"qps": qps, "cap_gb": cap_gb, "requests": len(rq)}
+        for io in ("host", "resident"):
+            inits = {q.rid: (host_t if io == "host" else dev_t)[q.r] for q in rq}
+            outs = {q.rid: host_o[q.r] for q in rq} if io == "host" else None
+            modes = [("continuous", 0, 1), ("one_at_a_time", 1, 1)]
+            if io == "host":  # uploads not held back: interleaved with read-backs
+                modes.insert(1, ("continuous_no_transfer_window", 0, 0))
+            for mode, k, window in modes:
+                server.set_max_active(k)
+                server.set_transfer_window(window)
+                server.replay(rq[:16], inits, outs)  # warm-up (first-call costs)
+                st = server.replay(rq, inits, outs)
+                summ = st.summary()
+                summ["cells_per_s"] = cells / max(st.makespan, 1e-12)
+                row[f"{io}_{mode}"] = summ
+                log(f"serving qps={qps:.0f} {io:8s} {mode:29s}: p50 {summ['p50_ms']:8.2f} ms "
+                    f"p99 {summ['p99_ms']:8.2f} ms  {summ['cells_per_s'] / 1e9:8.1f} Gcells/s "
+                    f"makespan {st.makespan * 1e3:8.1f} ms")
+        server.set_max_active(0)
+        server.set_transfer_window(1)
+        results.append(row)
+    stats = server.stats()
+    server.close()
+    del dev_t, host_t, host_o
+    torch.cuda.empty_cache()
     return {"tune": tune.as_dict(), "requests": count, "horizon_cells": horizon_cells,
-            "budget_cells": budget_cells, "by_qps": results}
+            "budget_cells": budget_cells, "server": {k: int(v) for k, v in stats.items()},
+            "by_qps": results}
 
 
 def bench_compact_large(torch, sg, r, rho, steps, reps):

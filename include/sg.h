@@ -158,6 +158,18 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
                        const uint8_t *d_in, uint8_t *d_out, uint8_t *d_work,
                        void *stream);
 
+/* Launch-shape autotuner of sg_ca_steps for one gasket: times `steps`
+ * generations from d_in on the caller's buffers (d_out and d_work written,
+ * d_in only read; d_work needed) for every tile side rho in {32, 64, 128,
+ * 256} that fits in n and every steps_per_pass in {8, 16, 32}, one warm-up
+ * call and one timed call each (HIP events on `stream`), and returns the
+ * fastest shape and its time in milliseconds.  Synchronises the stream.
+ * Errors: SG_EINVAL (as sg_ca_steps for any candidate, steps < 1, n < 32,
+ * NULL outputs), SG_EALIAS, SG_EHIP. */
+SG_API int sg_ca_steps_autotune(int map, int r, int steps, const uint8_t *d_in, uint8_t *d_out,
+                                uint8_t *d_work, int *best_rho, int *best_steps_per_pass,
+                                float *best_ms, void *stream);
+
 /* One explicit diffusion step on the gasket in FP32 (a nearest-neighbour
  * application, Section I): for every gasket cell,
  *   out = u + alpha * sum_{nb in W, E, N, S; in grid and in gasket} (u_nb - u);
@@ -374,11 +386,12 @@ SG_API int sg_batch_stats(const sg_batch *batch, uint64_t *passes, uint64_t *cel
 /* Frees the handle, its graph and its device tables (NULL is ignored). */
 SG_API void sg_batch_destroy(sg_batch *batch);
 
-/* Times every candidate shape (rho in {64, 128, 256}, 8 or 16 generations
- * per pass, 0/2/4/8 groups per compute unit,
- * 256/512 threads) by running the batch on `stream` (writes the gaskets'
- * out/work buffers, never their inputs) and returns the fastest shape and
- * its time.  Synchronises the stream.  Errors as sg_batch_create. */
+/* Times every candidate shape (rho in {64, 128, 256}, 8, 16 or 32
+ * generations per pass, 0/2/4/8 groups per compute unit, 256/512 threads)
+ * by running the batch on `stream` (writes the gaskets' out/work buffers,
+ * never their inputs) and returns the fastest shape and its time.  This is
+ * the launch-shape autotuner of the batched path; a single gasket is a batch
+ * of one.  Synchronises the stream.  Errors as sg_batch_create. */
 SG_API int sg_batch_autotune(const sg_gasket *gaskets, int count, sg_tune *best,
                              float *best_ms, void *stream);
 
@@ -449,6 +462,7 @@ typedef struct sg_server_stats {
      * the cap, since idle pooled buffers of other levels are freed before an
      * allocation would pass it */
     uint64_t allocated_bytes, max_allocated_bytes;
+    uint64_t transferring;  /* host requests now uploading or reading back */
 } sg_server_stats;
 
 /* tune: the batched pass's launch shape (as sg_batch_create); max_requests:
@@ -475,10 +489,59 @@ SG_API int sg_server_reserve(sg_server *s, const int32_t *levels, int count);
 SG_API int sg_server_submit(sg_server *s, int r, int steps, const uint8_t *d_init,
                             uint8_t *d_out, uint64_t tag);
 
-/* One scheduling round; reports up to max_done finished (or rejected)
- * requests in `done` (host array) and their number in *n_done.
+/* Queues a request whose state lives in host memory: h_init (pinned host
+ * memory, e.g. from hipHostMalloc, n x n, 0 off the gasket) is uploaded on a
+ * copy stream of the server's when a round admits the request, the request
+ * joins passes once its upload has ended, and when it finishes its result is
+ * read back into h_out (pinned host n x n, or NULL) on a second copy stream
+ * while other requests' passes run; it is reported done (with result =
+ * h_out) in the first round after the read-back has ended.  Its buffers are
+ * held from admission to that report.  h_init must stay valid and unchanged,
+ * and h_out unread, until the request is reported.
+ * Errors: SG_EINVAL, SG_ENOMEM (max_requests reached). */
+SG_API int sg_server_submit_host(sg_server *s, int r, int steps, const uint8_t *h_init,
+                                 uint8_t *h_out, uint64_t tag);
+
+/* Admits at most max_active requests in flight at once (uploading, in
+ * passes, or reading back); 0 (the default) sets no limit.  With 1 the
+ * server runs one request at a time through the same loop.
+ * Errors: SG_EINVAL. */
+SG_API int sg_server_set_max_active(sg_server *s, int max_active);
+
+/* A host request's upload starts (the request is admitted) only while fewer
+ * than `window` host requests are uploading or reading back; 0 sets no
+ * limit.  The default is 1: copies in both directions share one host link,
+ * so first-in first-out transfers give each request its result soonest,
+ * while passes still overlap them.  Errors: SG_EINVAL. */
+SG_API int sg_server_set_transfer_window(sg_server *s, int window);
+
+/* One scheduling round: host requests whose upload or read-back ended move
+ * on, admission, then the passes; reports up to max_done finished (or
+ * rejected) requests in `done` (host array) and their number in *n_done.
+ * Waits for the server's stream when it queued work on it, never for the
+ * copy streams.
  * Errors: SG_EINVAL, SG_ENOMEM, SG_EHIP. */
 SG_API int sg_server_step(sg_server *s, sg_server_done *done, int max_done, int *n_done);
+
+/* One request of a replay: submitted once `arrival_s` seconds have passed. */
+typedef struct sg_server_request {
+    double arrival_s;      /* seconds after the replay starts; non-decreasing */
+    int32_t r, steps;
+    const uint8_t *init;   /* device state, or pinned host state if host != 0 */
+    uint8_t *out;          /* device / pinned host copy of the result, or NULL */
+    int32_t host;          /* 1: init and out are pinned host memory */
+} sg_server_request;
+
+/* Serves `count` requests arriving in real time on an idle server: request i
+ * is submitted once arrival_s[i] seconds have passed since the call began,
+ * and rounds run whenever requests are open.  finish_s[i] receives the
+ * seconds, on the same clock, at which request i was reported (so its
+ * latency is finish_s[i] - arrival_s[i]) and rejected[i] whether it was
+ * rejected.  Returns when every request has been reported.
+ * Errors: SG_EINVAL (arrivals out of order or negative, a busy server, NULL
+ * arrays), and those of submission and of sg_server_step. */
+SG_API int sg_server_replay(sg_server *s, const sg_server_request *reqs, int count,
+                            double *finish_s, int32_t *rejected);
 
 SG_API int sg_server_get_stats(const sg_server *s, sg_server_stats *out);
 

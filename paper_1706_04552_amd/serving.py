@@ -328,6 +328,70 @@ class NativeServer:
         po = sg._dev(out, self._u8, (1 << r) * (1 << r), "out") if out is not None else None
         sg._check(sg.load().sg_server_submit(self._h, r, steps, pi, po, tag), "sg_server_submit")
 
+    def submit_host(self, r: int, steps: int, h_init, tag: int, h_out=None):
+        """h_init (and h_out, if given): pinned uint8 n x n CPU tensors kept
+        alive, and h_out unread, until the request is reported."""
+        n2 = (1 << r) * (1 << r)
+        for name, t in (("h_init", h_init), ("h_out", h_out)):
+            if t is None:
+                continue
+            if t.is_cuda or not t.is_pinned() or t.dtype != self._u8 or t.numel() != n2 \
+                    or not t.is_contiguous():
+                raise ValueError(f"{name}: a pinned contiguous uint8 CPU tensor of {n2} bytes")
+        self._sg._check(self._sg.load().sg_server_submit_host(
+            self._h, r, steps, h_init.data_ptr(), h_out.data_ptr() if h_out is not None else None,
+            tag), "sg_server_submit_host")
+
+    def set_max_active(self, k: int):
+        """At most k requests in flight (0: no limit; 1: one at a time)."""
+        self._sg._check(self._sg.load().sg_server_set_max_active(self._h, int(k)),
+                        "sg_server_set_max_active")
+
+    def set_transfer_window(self, k: int):
+        """At most k host requests uploading or reading back (0: no limit)."""
+        self._sg._check(self._sg.load().sg_server_set_transfer_window(self._h, int(k)),
+                        "sg_server_set_transfer_window")
+
+    def replay(self, requests: Sequence[Request], inits: Dict[int, object],
+               outs: Optional[Dict[int, object]] = None) -> "ServeStats":
+        """Serves `requests` in native code (sg_server_replay): each is
+        submitted at its arrival time and rounds run while any is open.
+        inits[rid] / outs[rid]: CUDA tensors, or pinned CPU tensors for
+        requests whose state is uploaded and read back by the server."""
+        order = sorted(requests, key=lambda q: (q.arrival, q.rid))
+        arr = (self._sg.sg_server_request * max(1, len(order)))()
+        n2 = lambda r: (1 << r) * (1 << r)  # noqa: E731
+        for i, q in enumerate(order):
+            init = inits[q.rid]
+            out = outs.get(q.rid) if outs else None
+            host = not init.is_cuda
+            if host:
+                for t in (init, out):
+                    if t is not None and (t.is_cuda or not t.is_pinned() or t.numel() != n2(q.r)):
+                        raise ValueError("host requests need pinned CPU tensors of n x n bytes")
+                pi, po = init.data_ptr(), (out.data_ptr() if out is not None else None)
+            else:
+                pi = self._sg._dev(init, self._u8, n2(q.r), "init").value
+                po = (self._sg._dev(out, self._u8, n2(q.r), "out").value
+                      if out is not None else None)
+            arr[i].arrival_s, arr[i].r, arr[i].steps = float(q.arrival), q.r, q.steps
+            arr[i].init, arr[i].out, arr[i].host = pi, po, int(host)
+        fin = (self._ct.c_double * max(1, len(order)))()
+        rej = (self._ct.c_int32 * max(1, len(order)))()
+        s0 = self.stats()
+        self._sg._check(self._sg.load().sg_server_replay(self._h, arr, len(order), fin, rej),
+                        "sg_server_replay")
+        s = self.stats()
+        st = ServeStats()
+        for i, q in enumerate(order):
+            st.results.append(Result(q.rid, q.r, q.steps, q.arrival, fin[i], fin[i],
+                                     rejected=bool(rej[i])))
+        st.makespan = max((fin[i] for i in range(len(order))), default=0.0)
+        st.iterations, st.passes = s["rounds"] - s0["rounds"], s["passes"] - s0["passes"]
+        # the server's maxima cover its whole life, not this replay alone
+        st.max_resident_bytes, st.max_active = s["max_resident_bytes"], s["max_active"]
+        return st
+
     def step(self):
         """One scheduling round: [(tag, rejected), ...] of the requests it ended."""
         n = self._ct.c_int()

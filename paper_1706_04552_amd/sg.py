@@ -65,10 +65,15 @@ class sg_server_stats(ctypes.Structure):
     _fields_ = [(f, ctypes.c_uint64) for f in
                 ("rounds", "passes", "completed", "rejected", "cell_steps", "max_resident_bytes",
                  "max_active", "queued", "active", "resident_bytes", "allocated_bytes",
-                 "max_allocated_bytes")]
+                 "max_allocated_bytes", "transferring")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class sg_server_request(ctypes.Structure):
+    _fields_ = [("arrival_s", ctypes.c_double), ("r", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("init", ctypes.c_void_p), ("out", ctypes.c_void_p), ("host", ctypes.c_int32)]
 
 
 # Every symbol declared in include/sg.h, with its ctypes signature.
@@ -132,6 +137,18 @@ _SIGNATURES = {
                                         ctypes.c_void_p, ctypes.c_uint64]),
     "sg_server_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sg_server_done), ctypes.c_int,
                                       ctypes.POINTER(ctypes.c_int)]),
+    "sg_ca_steps_autotune": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_float), ctypes.c_void_p]),
+    "sg_server_submit_host": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64]),
+    "sg_server_set_max_active": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "sg_server_set_transfer_window": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "sg_server_replay": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sg_server_request),
+                                        ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int32)]),
     "sg_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(sg_server_stats)]),
     "sg_server_destroy": (None, [ctypes.c_void_p]),
     "sg_tune_default": (ctypes.c_int, [_tunep]),
@@ -297,6 +314,21 @@ def sg_ca_steps(map_kind, r: int, rho: int, steps: int, d_in: torch.Tensor,
     _check(load().sg_ca_steps(_map(map_kind), r, rho, steps, steps_per_pass, pi, po, pw,
                               _stream(stream)), "sg_ca_steps")
     return d_out
+
+
+def sg_ca_steps_autotune(map_kind, r: int, steps: int, d_in: torch.Tensor, d_out: torch.Tensor,
+                         d_work: torch.Tensor, stream=None):
+    """The fastest (rho, steps_per_pass) of sg_ca_steps for this gasket and
+    its time in ms, timed on these buffers (d_out and d_work are written)."""
+    n2 = _n2(r)
+    pi = _dev(d_in, torch.uint8, n2, "d_in")
+    po = _dev(d_out, torch.uint8, n2, "d_out")
+    pw = _dev(d_work, torch.uint8, n2, "d_work")
+    rho, spp, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    _check(load().sg_ca_steps_autotune(_map(map_kind), r, steps, pi, po, pw, ctypes.byref(rho),
+                                       ctypes.byref(spp), ctypes.byref(ms), _stream(stream)),
+           "sg_ca_steps_autotune")
+    return rho.value, spp.value, ms.value
 
 
 def sg_diffuse_step(map_kind, r: int, rho: int, d_in: torch.Tensor, d_out: torch.Tensor,

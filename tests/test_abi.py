@@ -223,6 +223,20 @@ print(res, lib.sg_last_hip_error().decode())
     assert line.split("]", 1)[1].strip()  # the HIP error text is kept
 
 
+def test_ca_steps_autotune_validation(lib):
+    from paper_1706_04552_amd import sg
+    a, b, w = 0x100000, 0x7000000000, 0x7100000000
+    rho, spp, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_float()
+    out = (ctypes.byref(rho), ctypes.byref(spp), ctypes.byref(ms))
+    assert lib.sg_ca_steps_autotune(0, 10, 0, a, b, w, *out, None) == sg.SG_EINVAL   # steps < 1
+    assert lib.sg_ca_steps_autotune(0, 4, 8, a, b, w, *out, None) == sg.SG_EINVAL    # n < 32
+    assert lib.sg_ca_steps_autotune(2, 10, 8, a, b, w, *out, None) == sg.SG_EINVAL   # map kind
+    assert lib.sg_ca_steps_autotune(0, 10, 8, a, b, None, *out, None) == sg.SG_EINVAL  # no work
+    assert lib.sg_ca_steps_autotune(0, 10, 8, a, a + 64, w, *out, None) == sg.SG_EALIAS
+    assert lib.sg_ca_steps_autotune(0, 10, 8, a, b, w, None, ctypes.byref(spp),
+                                    ctypes.byref(ms), None) == sg.SG_EINVAL
+
+
 def test_diffuse_steps_validation(lib):
     from paper_1706_04552_amd import sg
     a, b, w = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x7000000000), ctypes.c_void_p(0x7100000000)
@@ -358,6 +372,13 @@ def test_server_validation_on_the_host(lib):
     n = ctypes.c_int(-1)
     assert lib.sg_server_step(None, None, 0, ctypes.byref(n)) == sg.SG_EINVAL
     assert lib.sg_server_get_stats(None, None) == sg.SG_EINVAL
+    assert lib.sg_server_submit_host(None, 8, 1, 0x1000, None, 0) == sg.SG_EINVAL
+    assert lib.sg_server_set_max_active(None, 1) == sg.SG_EINVAL
+    assert lib.sg_server_set_transfer_window(None, 1) == sg.SG_EINVAL
+    fin = (ctypes.c_double * 1)()
+    rej = (ctypes.c_int32 * 1)()
+    reqs = (sg.sg_server_request * 1)()
+    assert lib.sg_server_replay(None, reqs, 1, fin, rej) == sg.SG_EINVAL
     lib.sg_server_destroy(None)
 
 

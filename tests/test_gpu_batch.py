@@ -296,3 +296,62 @@ def test_python_executor_device_memory_stays_under_the_cap():
             q = reqs[res.rid - reqs[0].rid]
             oracle_check(q.r, q.state, q.steps, res.output)
     ex.close()
+
+
+def _pinned(a: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+
+
+@pytest.mark.parametrize("max_active,window", [(0, 1), (1, 1), (3, 1), (0, 0), (0, 2)])
+def test_native_server_replay_host_and_device_requests(max_active, window):
+    """Requests arriving in real time through the native replay loop, half
+    with pinned host states (uploaded at admission, read back when done) and
+    half with device states; every result equals the gasket run alone and
+    the oracle, and max_active bounds the requests in flight."""
+    rng = np.random.default_rng(41 + max_active)
+    reqs, inits, outs = [], {}, {}
+    for i in range(24):
+        r = int(rng.integers(6, 11))
+        steps = int(rng.integers(0, 50))
+        a0 = inputs.bernoulli_state(r, 0.5, 1200 + i)
+        q = Request(i, float(rng.uniform(0, 0.01)), r, steps, a0)
+        reqs.append(q)
+        if i % 2:
+            inits[i], outs[i] = _pinned(a0), torch.zeros(a0.shape, dtype=torch.uint8).pin_memory()
+        else:
+            inits[i] = torch.from_numpy(a0).cuda()
+            outs[i] = torch.zeros_like(inits[i])
+    note(f"native server replay: 24 requests (12 host, 12 device), max_active={max_active}")
+    server = NativeServer(B.make_tune(64, 8, 2, 256), 8 * footprint(10), 64)
+    server.set_max_active(max_active)
+    server.set_transfer_window(window)
+    st = server.replay(reqs, inits, outs)
+    stats = server.stats()
+    server.close()
+    assert len(st.results) == 24 and not any(x.rejected for x in st.results)
+    assert all(x.finished >= x.arrival for x in st.results)
+    if max_active:
+        assert stats["max_active"] <= max_active
+    assert stats["completed"] == 24 and stats["transferring"] == 0
+    for q in reqs:
+        got = outs[q.rid].cpu().numpy() if not outs[q.rid].is_cuda else outs[q.rid].cpu().numpy()
+        g = B.Gasket(q.r, q.steps, torch.from_numpy(q.state).cuda(),
+                     torch.zeros(q.state.shape, dtype=torch.uint8, device="cuda"),
+                     torch.zeros(q.state.shape, dtype=torch.uint8, device="cuda"))
+        assert np.array_equal(got, solo(g, T=8).cpu().numpy()), q.rid
+        oracle_check(q.r, q.state, q.steps, got)
+
+
+def test_ca_steps_autotune_single_gasket():
+    r, steps = 12, 40
+    note(f"sg_ca_steps_autotune r={r} {steps} generations")
+    a0 = inputs.bernoulli_state(r, 0.5, 1300)
+    inp = torch.from_numpy(a0).cuda()
+    out, work = torch.zeros_like(inp), torch.zeros_like(inp)
+    rho, spp, ms = sg.sg_ca_steps_autotune("lambda", r, steps, inp, out, work)
+    assert rho in (32, 64, 128, 256) and spp in (8, 16, 32) and ms > 0
+    assert torch.equal(inp, torch.from_numpy(a0).cuda())  # the input is read only
+    out.zero_()
+    sg.sg_ca_steps("lambda", r, rho, steps, inp, out, work, steps_per_pass=spp)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), O.life_steps_sparse(r, a0, steps))
