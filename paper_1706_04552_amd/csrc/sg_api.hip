@@ -168,9 +168,13 @@ SG_API int sg_ca_step(int map, int r, int rho, const uint8_t *d_in, uint8_t *d_o
   return hip_status(sg::launch_life(a, d_in, d_out));
 }
 
-SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
-                       const uint8_t *d_in, uint8_t *d_out, uint8_t *d_work, void *stream) {
-  sg::PassArgs a;
+}  // extern "C"
+
+namespace {
+// The checks of sg_ca_steps, before any HIP call; fills `a` and resolves
+// steps_per_pass = 0 to the library's choice.
+int ca_steps_args(int map, int r, int rho, int steps, int &steps_per_pass, const uint8_t *d_in,
+                  const uint8_t *d_out, const uint8_t *d_work, void *stream, sg::PassArgs &a) {
   const int st = pass_args(map, r, rho, stream, a);
   if (st != SG_OK) return st;
   if (steps < 0 || steps_per_pass < 0 || steps_per_pass > sg::kMaxStepsPerPass) return SG_EINVAL;
@@ -188,6 +192,20 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
     if (!d_work || misaligned(d_work)) return SG_EINVAL;
     if (overlaps(d_work, d_in, bytes) || overlaps(d_work, d_out, bytes)) return SG_EALIAS;
   }
+  return SG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
+                       const uint8_t *d_in, uint8_t *d_out, uint8_t *d_work, void *stream) {
+  sg::PassArgs a;
+  const int st = ca_steps_args(map, r, rho, steps, steps_per_pass, d_in, d_out, d_work, stream, a);
+  if (st != SG_OK) return st;
+  const bool tb_ok = sg::life_tb_dense_supported(rho);
+  const size_t bytes = ((size_t)1 << r) * ((size_t)1 << r);
+  const int passes = (steps + steps_per_pass - 1) / steps_per_pass;
   SG_INJECT();
   if (steps == 0)
     return hip_status(hipMemcpyAsync(d_out, d_in, bytes, hipMemcpyDeviceToDevice, a.stream));
@@ -203,6 +221,61 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
     src = dst;
   }
   return SG_OK;
+}
+
+SG_API int sg_ca_steps_autotune(int map, int r, int steps, const uint8_t *d_in, uint8_t *d_out,
+                                uint8_t *d_work, int *best_rho, int *best_steps_per_pass,
+                                float *best_ms, void *stream) {
+  if (!best_rho || !best_steps_per_pass || !best_ms || steps < 1 || !d_work) return SG_EINVAL;
+  // every candidate is checked before any is timed
+  const int rhos[] = {32, 64, 128, 256}, spps[] = {8, 16, 32};
+  int candidates = 0;
+  for (int rho : rhos) {
+    if (r < 0 || r > SG_MAX_R || rho > (1 << r)) continue;
+    for (int T : spps) {
+      sg::PassArgs a;
+      int spp = T;
+      const int st = ca_steps_args(map, r, rho, steps, spp, d_in, d_out, d_work, stream, a);
+      if (st != SG_OK) return st;
+      ++candidates;
+    }
+  }
+  if (candidates == 0) return SG_EINVAL;
+  SG_INJECT();
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return SG_EHIP;
+  }
+  int status = SG_OK;
+  float best = -1.0f;
+  for (int rho : rhos) {
+    if (rho > (1 << r)) continue;
+    for (int T : spps) {
+      int st = sg_ca_steps(map, r, rho, steps, T, d_in, d_out, d_work, stream);  // warm-up
+      if (st == SG_OK && hipEventRecord(e0, s) != hipSuccess) st = SG_EHIP;
+      if (st == SG_OK) st = sg_ca_steps(map, r, rho, steps, T, d_in, d_out, d_work, stream);
+      if (st == SG_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        st = SG_EHIP;
+      float ms = 0.0f;
+      if (st == SG_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = SG_EHIP;
+      if (st != SG_OK) {
+        status = st;
+        break;
+      }
+      if (best < 0.0f || ms < best) {
+        best = ms;
+        *best_rho = rho;
+        *best_steps_per_pass = T;
+      }
+    }
+    if (status != SG_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status == SG_OK) *best_ms = best;
+  return status;
 }
 
 SG_API int sg_diffuse_steps(int map, int r, int rho, int steps, int steps_per_pass,
