@@ -77,6 +77,7 @@ struct Pass {
   std::vector<sg::BatchItem> items;
   uint64_t total_tiles = 0;
   int max_steps = 0;
+  uint64_t touched = 0;  // bytes the pass reads and writes (life_touched_bytes)
 };
 
 struct Plan {
@@ -134,6 +135,7 @@ int make_plan(const sg_gasket *gs, int count, const sg_tune &t, Plan &plan) {
       it.tile_begin = pass.total_tiles;
       pass.total_tiles += pow3(g.r - it.k);
       pass.max_steps = std::max(pass.max_steps, (int)it.steps);
+      pass.touched += sg::life_touched_bytes(g.r);
       pass.items.push_back(it);
     }
   }
@@ -152,7 +154,7 @@ int launch_plan(const Plan &plan, const sg_tune &t, const sg::BatchItem *d_table
     const Pass &pass = plan.passes[p];
     const hipError_t e = sg::launch_life_tb_batch(
         t.rho, t.threads, d_tables + offsets[p], (int)pass.items.size(), pass.total_tiles,
-        pass.max_steps, groups_for(t, pass.total_tiles), s);
+        pass.max_steps, groups_for(t, pass.total_tiles), sg::life_stream_stores(pass.touched), s);
     if (e != hipSuccess) return SG_EHIP;
   }
   return SG_OK;
@@ -396,11 +398,12 @@ SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
     if (ctx->pending[slot] && hipEventSynchronize(ctx->staged[slot]) != hipSuccess) return SG_EHIP;
     sg::BatchItem *h_stage = ctx->h_stage + (size_t)slot * ctx->capacity;
     sg::BatchItem *d_items = ctx->d_items + (size_t)slot * ctx->capacity;
-    uint64_t tiles = 0;
+    uint64_t tiles = 0, touched = 0;
     int m = 0;
     for (int i = 0; i < count; ++i) {
       const sg_pass_item &it = items[i];
       if (it.steps == 0) continue;
+      touched += sg::life_touched_bytes(it.r);
       sg::BatchItem b;
       b.src = it.src;
       b.dst = it.dst;
@@ -419,7 +422,8 @@ SG_API int sg_pass_run(sg_pass_ctx *ctx, const sg_pass_item *items, int count,
     ctx->pending[slot] = true;
     ctx->next = (slot + 1) % kPassRing;
     return hip_err(sg::launch_life_tb_batch(tune->rho, tune->threads, d_items, m, tiles,
-                                            max_steps, groups_for(*tune, tiles), s));
+                                            max_steps, groups_for(*tune, tiles),
+                                            sg::life_stream_stores(touched), s));
   });
 }
 
@@ -495,11 +499,12 @@ SG_API int sg_pass_run_static(const sg_pass_item *items, int count, const sg_tun
   hipStream_t s = (hipStream_t)stream;
   const int kmax = rho_log2(tune->rho);
   StageChunk chunk;
-  uint64_t tiles = 0;
+  uint64_t tiles = 0, touched = 0;
   int m = 0, c = 0;
   for (int i = 0; i < count; ++i) {
     const sg_pass_item &it = items[i];
     if (it.steps == 0) continue;
+    touched += sg::life_touched_bytes(it.r);
     sg::BatchItem &b = chunk.items[c++];
     b.src = it.src;
     b.dst = it.dst;
@@ -517,7 +522,8 @@ SG_API int sg_pass_run_static(const sg_pass_item *items, int count, const sg_tun
     }
   }
   return hip_err(sg::launch_life_tb_batch(tune->rho, tune->threads, table, m, tiles, max_steps,
-                                          groups_for(*tune, tiles), s));
+                                          groups_for(*tune, tiles),
+                                          sg::life_stream_stores(touched), s));
 }
 
 SG_API void sg_pass_ctx_destroy(sg_pass_ctx *ctx) {

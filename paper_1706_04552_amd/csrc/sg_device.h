@@ -181,21 +181,42 @@ __device__ __forceinline__ void load_row(U8Row<RHO> &row, const uint8_t *p) {
   }
 }
 
-template <int RHO>
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Stores a row of a tile.  STREAM: non-temporal stores, for passes that read
+// the previous state and write the next one, so the written lines do not
+// take cache space from the reads (neighbouring tiles share the read halo
+// rows); the write pass, which only writes, keeps ordinary stores.
+template <int RHO, bool STREAM = false>
 __device__ __forceinline__ void store_row(uint8_t *p, const U8Row<RHO> &row) {
   if constexpr (RHO == 1) {
     p[0] = (uint8_t)row.w[0];
   } else if constexpr (RHO == 2) {
     *reinterpret_cast<uint16_t *>(p) = (uint16_t)row.w[0];
   } else if constexpr (RHO == 4) {
-    *reinterpret_cast<uint32_t *>(p) = row.w[0];
+    if constexpr (STREAM)
+      __builtin_nontemporal_store(row.w[0], reinterpret_cast<uint32_t *>(p));
+    else
+      *reinterpret_cast<uint32_t *>(p) = row.w[0];
   } else if constexpr (RHO == 8) {
-    *reinterpret_cast<uint2 *>(p) = make_uint2(row.w[0], row.w[1]);
+    if constexpr (STREAM) {
+      const u32x2 v = {row.w[0], row.w[1]};
+      __builtin_nontemporal_store(v, reinterpret_cast<u32x2 *>(p));
+    } else {
+      *reinterpret_cast<uint2 *>(p) = make_uint2(row.w[0], row.w[1]);
+    }
   } else {
 #pragma unroll
-    for (int k = 0; k < RHO / 16; ++k)
-      reinterpret_cast<uint4 *>(p)[k] =
-          make_uint4(row.w[4 * k], row.w[4 * k + 1], row.w[4 * k + 2], row.w[4 * k + 3]);
+    for (int k = 0; k < RHO / 16; ++k) {
+      if constexpr (STREAM) {
+        const u32x4 v = {row.w[4 * k], row.w[4 * k + 1], row.w[4 * k + 2], row.w[4 * k + 3]};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p) + k);
+      } else {
+        reinterpret_cast<uint4 *>(p)[k] =
+            make_uint4(row.w[4 * k], row.w[4 * k + 1], row.w[4 * k + 2], row.w[4 * k + 3]);
+      }
+    }
   }
 }
 

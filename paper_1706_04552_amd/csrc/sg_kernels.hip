@@ -346,7 +346,7 @@ __global__ __launch_bounds__((Strip<RHO, 16, NT>::WGS)) void k_write_strip(
 template <int RHO, bool LAMBDA, int NT>
 __global__ __launch_bounds__((Strip<RHO, 16, NT>::WGS)) void k_life_strip(
     const uint8_t *__restrict__ in, uint8_t *__restrict__ out, int r, int rb,
-    uint64_t tile_base, uint64_t ntiles) {
+    uint64_t tile_base, uint64_t ntiles, int stream_out) {
   using G = Strip<RHO, 16, NT>;
   const int slot = threadIdx.x / G::LPT, lt = threadIdx.x % G::LPT;
   const int band = lt / G::CPR, c = lt % G::CPR;
@@ -397,7 +397,13 @@ __global__ __launch_bounds__((Strip<RHO, 16, NT>::WGS)) void k_life_strip(
       O.w[k] = ~z & row_mask_word<16>(k, ym) & chunk_on;
     }
     constexpr size_t smask = ~(size_t)(Granules<RHO>::STORE - 1);
-    if (((x & smask) & y) == 0) store_row<16>(out + y * n + x, O);
+    if (((x & smask) & y) == 0) {
+      // whole granules (rho >= 64) may stream; 32-byte rows never do
+      if (RHO >= 64 && stream_out)
+        store_row<16, true>(out + y * n + x, O);
+      else
+        store_row<16>(out + y * n + x, O);
+    }
   }
 }
 
@@ -480,7 +486,10 @@ hipError_t launch_tiles(uint64_t ntiles, int tpg, hipStream_t s, F &&launch_one)
 // Workgroup size of a one-step pass: launches of fewer than kSmallLaunchWaves
 // waves (small gaskets, where a pass is one latency chain) run one wave per
 // workgroup, so they spread over more CUs; larger launches run four.
-constexpr uint64_t kSmallLaunchWaves = 2048;
+#ifndef SG_SMALL_LAUNCH_WAVES
+#define SG_SMALL_LAUNCH_WAVES 2048
+#endif
+constexpr uint64_t kSmallLaunchWaves = SG_SMALL_LAUNCH_WAVES;
 inline bool small_launch(uint64_t ntiles, int lanes_per_tile) {
   return ntiles * (uint64_t)lanes_per_tile < kSmallLaunchWaves * 64;
 }
@@ -518,8 +527,9 @@ hipError_t write_strip(const PassArgs &a, uint8_t *d, uint32_t value) {
 
 template <int RHO>
 hipError_t life_strip(const PassArgs &a, const uint8_t *in, uint8_t *out) {
+  const int stream_out = life_stream_stores(life_touched_bytes(a.r)) ? 1 : 0;
   SG_LAUNCH_PASS(k_life_strip, SG_STRIP16_TPG, SG_STRIP16_WGS, (Strip<RHO, 16, 64>::LPT),
-                 in, out, a.r, a.rb, base, a.ntiles);
+                 in, out, a.r, a.rb, base, a.ntiles, stream_out);
 }
 
 template <int RHO>

@@ -15,6 +15,19 @@ bool inject_hip_error();
 // SG_OK, or SG_EHIP with the HIP error's text kept for sg_last_hip_error.
 int status_of(hipError_t e);
 
+// Output stores of a life pass go non-temporal when the bytes it moves
+// exceed the 256 MB Infinity Cache: then its output would only evict the
+// input lines that neighbouring tiles still read, while a working set that
+// fits (r <= 15) is served from the cache and ordinary stores are faster.
+// A uint8 state touches about (4/3)^6 * 3^r bytes in 64-byte granules.
+constexpr uint64_t kCacheBytes = 256ull << 20;
+inline uint64_t life_touched_bytes(int r) {
+  uint64_t v = 1;
+  for (int i = 0; i < r; ++i) v *= 3;
+  return 2 * v * 4096 / 729;  // input and output state
+}
+inline bool life_stream_stores(uint64_t touched_bytes) { return touched_bytes > kCacheBytes; }
+
 // One pass over the tiles of a map.
 struct PassArgs {
   int r;            // level: n = 2^r
@@ -73,9 +86,10 @@ struct BatchItem {
   int16_t steps;        // generations in this pass
   int16_t k;            // this item's tile side is 2^k: 6, 7 or 8 (64, 128, 256)
 };
-// Tiles of every side up to max_rho may appear in one launch.
+// Tiles of every side up to max_rho may appear in one launch.  stream_out:
+// non-temporal output stores (life_stream_stores of the items' bytes).
 hipError_t launch_life_tb_batch(int max_rho, int threads, const BatchItem *d_items, int count,
                                 uint64_t total_tiles, int max_steps, int groups,
-                                hipStream_t stream);
+                                bool stream_out, hipStream_t stream);
 
 }  // namespace sg

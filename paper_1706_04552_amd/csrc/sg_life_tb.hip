@@ -40,15 +40,11 @@ namespace {
 #ifndef SG_TB_SEG_ROWS
 #define SG_TB_SEG_ROWS 5
 #endif
-#ifndef SG_TB_LOAD_BATCH
-#define SG_TB_LOAD_BATCH 4
-#endif
 template <int RHO>
 constexpr int tb_threads() {
   return SG_TB_THREADS > 0 ? SG_TB_THREADS : (RHO >= 256 ? 512 : 256);
 }
 constexpr int kSegRows = SG_TB_SEG_ROWS;      // rows per vertical segment of a generation
-constexpr int kLoadBatch = SG_TB_LOAD_BATCH;  // global loads in flight per thread
 
 // Plane pitch (words per plane row) for a region W words wide.  Threads that
 // run consecutive segments of one word column touch rows kSegRows apart; a
@@ -315,24 +311,28 @@ __device__ __forceinline__ void tb_load(const Mem &mem, int r, uint32_t bx, uint
   }
 }
 
-// A 16-byte store of a pass's output.  Streaming (non-temporal): nothing
-// reads the output within the pass, and keeping it out of the caches leaves
-// them to the region reads, whose halos neighbouring tiles share.
-__device__ __forceinline__ void store16_stream(uint8_t *p, const uint4 w) {
-  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  const u32x4 v = {w.x, w.y, w.z, w.w};
-  __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+// A 16-byte store of a pass's output; `stream`: non-temporal (nothing reads
+// the output within the pass, and a working set larger than the cache is
+// better left to the region reads, whose halos neighbouring tiles share).
+__device__ __forceinline__ void store16(uint8_t *p, const uint4 w, bool stream) {
+  if (stream) {
+    const u32x4 v = {w.x, w.y, w.z, w.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+  } else {
+    *reinterpret_cast<uint4 *>(p) = w;
+  }
 }
 
 // One tile pass: the rho x rho tile at block (bx, by) of the gasket of level
 // r advanced by T generations from mem.src to mem.dst, by NT threads, from
 // its region loads `ld` (issued by tb_load; a compact Mem is prepared).
 // `lds` holds tb_lds_bytes<RHO>(T) bytes (or more); the caller synchronises
-// the workgroup before reusing it.
+// the workgroup before reusing it.  stream_out: store the output
+// non-temporally (life_stream_stores).
 template <int RHO, int NT, class Mem>
 __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint32_t by, int T,
                                         uint32_t *lds, uint32_t *nseg_p,
-                                        const RegionLoads<RHO, NT> &ld) {
+                                        const RegionLoads<RHO, NT> &ld, bool stream_out) {
   uint32_t &nseg = *nseg_p;
   constexpr int kTbThreads = NT;
   // Region columns [X0-32, X0+RHO+32): the tile plus one 32-cell word each
@@ -341,7 +341,6 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   // its row whenever its first cell is on the gasket.
   constexpr int W = RHO / 32 + 2;     // region words per row
   constexpr int PW = plane_pitch(W);  // plane pitch (at least one zero guard word each side)
-  constexpr int CH = 2 * W;           // 16-byte chunks per region row
   constexpr int L = kSegRows;
   static_assert(L <= 8, "row bits of a segment are kept in 8 bits");
   static_assert(RHO % 32 == 0, "tile rows are whole 32-cell words");
@@ -354,8 +353,6 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   const int RP = NB * L;              // region rows rounded up to whole blocks
   const int PR = RP + 2;              // plane rows (zero guard row above, below)
   const int tid = threadIdx.x;
-  // chunks [jlo, CH - jlo) of a region row lie within T cells of the tile
-  const int jlo = T > 16 ? 0 : 1;
 
   // n <= 2^20, so cell coordinates (halo included) fit in 32-bit ints
   const int n = 1 << r;
@@ -511,7 +508,7 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
       const int ty = 16 * (int)(pr >> 4) + (lane >> 2);
       const int j = 4 * (int)(pr & 15u) + (lane & 3);  // tile chunk; region chunk j + 2
       const uint32_t bits = fin[((T + 1 + ty) * PW + 2 + (j >> 1)) * 2 + (j & 1)];
-      store16_stream(mem.dst(Y0 + ty, X0 + 16 * j), unpack16(bits));
+      store16(mem.dst(Y0 + ty, X0 + 16 * j), unpack16(bits), stream_out);
     }
   } else {
     constexpr int RPS = kTbThreads / TC;  // tile rows per round
@@ -524,7 +521,7 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
       // rho = 32: every row of a gasket block holds its cell 0)
       if (!Mem::kCompact && ((x & ~(G - 1)) & y) != 0) continue;
       const uint32_t bits = fin[f0 + ty * (2 * PW)];
-      store16_stream(mem.dst(y, x), unpack16(bits));
+      store16(mem.dst(y, x), unpack16(bits), stream_out);
     }
   }
 }
@@ -549,7 +546,8 @@ template <int RHO, bool LAMBDA>
 __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__restrict__ in,
                                                                uint8_t *__restrict__ out, int r,
                                                                int rb, uint64_t tile_base,
-                                                               uint64_t ntiles, int T) {
+                                                               uint64_t ntiles, int T,
+                                                               int stream_out) {
   constexpr int NT = tb_threads<RHO>();
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t nseg;
@@ -560,7 +558,7 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__
   const DenseMem mem{in, out, r};
   RegionLoads<RHO, NT> ld;
   tb_load<RHO, NT>(mem, r, bx, by, T, ld);
-  tb_tile<RHO, NT>(mem, r, bx, by, T, lds, &nseg, ld);
+  tb_tile<RHO, NT>(mem, r, bx, by, T, lds, &nseg, ld, stream_out != 0);
 }
 
 // One workgroup per tile of a gasket in block-compacted storage (lambda
@@ -568,7 +566,7 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__
 template <int RHO>
 __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb_compact(
     const uint8_t *__restrict__ in, uint8_t *__restrict__ out, int r, int rb,
-    uint64_t tile_base, uint64_t ntiles, int T) {
+    uint64_t tile_base, uint64_t ntiles, int T, int stream_out) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t nseg;
   __shared__ int32_t nbr[9];
@@ -581,16 +579,16 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb_compact(
   __syncthreads();  // the neighbour tiles' omegas
   RegionLoads<RHO, tb_threads<RHO>()> ld;
   tb_load<RHO, tb_threads<RHO>()>(mem, r, bx, by, T, ld);
-  tb_tile<RHO, tb_threads<RHO>()>(mem, r, bx, by, T, lds, &nseg, ld);
+  tb_tile<RHO, tb_threads<RHO>()>(mem, r, bx, by, T, lds, &nseg, ld, stream_out != 0);
 }
 
 // One tile of a batched pass: its region loads, then the tile pass.
 template <int RHO, int NT>
 __device__ __forceinline__ void batch_tile(const DenseMem &mem, int r, uint32_t bx, uint32_t by,
-                                           int T, uint32_t *lds, uint32_t *nseg) {
+                                           int T, uint32_t *lds, uint32_t *nseg, bool stream_out) {
   RegionLoads<RHO, NT> ld;
   tb_load<RHO, NT>(mem, r, bx, by, T, ld);
-  tb_tile<RHO, NT>(mem, r, bx, by, T, lds, nseg, ld);
+  tb_tile<RHO, NT>(mem, r, bx, by, T, lds, nseg, ld, stream_out);
 }
 
 // Many gaskets in one persistent launch: workgroups stride over the global
@@ -601,7 +599,8 @@ __device__ __forceinline__ void batch_tile(const DenseMem &mem, int r, uint32_t 
 // generation count.
 template <int MAXRHO, int NT>
 __global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restrict__ items,
-                                                      int count, uint64_t total_tiles) {
+                                                      int count, uint64_t total_tiles,
+                                                      int stream_out) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t nseg;
   for (uint64_t g = blockIdx.x; g < total_tiles; g += gridDim.x) {
@@ -615,11 +614,13 @@ __global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restric
     pass_decode((uint32_t)(g - it.tile_begin), it.r - it.k, bx, by);
     const DenseMem mem{it.src, it.dst, it.r};
     if (it.k == 6) {
-      batch_tile<64, NT>(mem, it.r, bx, by, it.steps, lds, &nseg);
+      batch_tile<64, NT>(mem, it.r, bx, by, it.steps, lds, &nseg, stream_out != 0);
     } else if (MAXRHO >= 128 && it.k == 7) {
-      batch_tile<(MAXRHO >= 128 ? 128 : 64), NT>(mem, it.r, bx, by, it.steps, lds, &nseg);
+      batch_tile<(MAXRHO >= 128 ? 128 : 64), NT>(mem, it.r, bx, by, it.steps, lds, &nseg,
+                                                 stream_out != 0);
     } else if (MAXRHO >= 256 && it.k == 8) {
-      batch_tile<(MAXRHO >= 256 ? 256 : 64), NT>(mem, it.r, bx, by, it.steps, lds, &nseg);
+      batch_tile<(MAXRHO >= 256 ? 256 : 64), NT>(mem, it.r, bx, by, it.steps, lds, &nseg,
+                                                 stream_out != 0);
     }
     __syncthreads();  // the next tile reuses the LDS planes
   }
@@ -637,15 +638,16 @@ size_t tb_lds_bytes(int T) {
 template <int RHO>
 hipError_t life_tb_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out) {
   const size_t lds = tb_lds_bytes<RHO>(T);
+  const int stream_out = life_stream_stores(life_touched_bytes(a.r)) ? 1 : 0;
   const uint64_t per_launch = 1ull << 22;
   for (uint64_t g0 = 0; g0 < a.ntiles; g0 += per_launch) {
     const uint64_t g = a.ntiles - g0 < per_launch ? a.ntiles - g0 : per_launch;
     if (a.lambda)
       hipLaunchKernelGGL((k_life_tb<RHO, true>), dim3((unsigned)g), dim3(tb_threads<RHO>()), lds,
-                         a.stream, in, out, a.r, a.rb, g0, a.ntiles, T);
+                         a.stream, in, out, a.r, a.rb, g0, a.ntiles, T, stream_out);
     else
       hipLaunchKernelGGL((k_life_tb<RHO, false>), dim3((unsigned)g), dim3(tb_threads<RHO>()), lds,
-                         a.stream, in, out, a.r, a.rb, g0, a.ntiles, T);
+                         a.stream, in, out, a.r, a.rb, g0, a.ntiles, T, stream_out);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -655,11 +657,13 @@ hipError_t life_tb_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out
 template <int RHO>
 hipError_t life_tb_compact_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out) {
   const size_t lds = tb_lds_bytes<RHO>(T);
+  // whole tiles are read and written: 2 states of ntiles * rho^2 bytes
+  const int stream_out = life_stream_stores(2 * a.ntiles * RHO * RHO) ? 1 : 0;
   const uint64_t per_launch = 1ull << 22;
   for (uint64_t g0 = 0; g0 < a.ntiles; g0 += per_launch) {
     const uint64_t g = a.ntiles - g0 < per_launch ? a.ntiles - g0 : per_launch;
     hipLaunchKernelGGL((k_life_tb_compact<RHO>), dim3((unsigned)g), dim3(tb_threads<RHO>()), lds,
-                       a.stream, in, out, a.r, a.rb, g0, a.ntiles, T);
+                       a.stream, in, out, a.r, a.rb, g0, a.ntiles, T, stream_out);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -668,13 +672,13 @@ hipError_t life_tb_compact_rho(const PassArgs &a, int T, const uint8_t *in, uint
 
 template <int RHO, int NT>
 hipError_t life_tb_batch_rho(const BatchItem *d_items, int count, uint64_t total_tiles,
-                             int max_steps, int groups, hipStream_t stream) {
+                             int max_steps, int groups, bool stream_out, hipStream_t stream) {
   // the largest tile side needs the most LDS
   const size_t lds = tb_lds_bytes<RHO>(max_steps);
   const uint64_t g = total_tiles < (uint64_t)groups ? total_tiles : (uint64_t)groups;
   if (g == 0) return hipSuccess;
   hipLaunchKernelGGL((k_life_tb_batch<RHO, NT>), dim3((unsigned)g), dim3(NT), lds, stream,
-                     d_items, count, total_tiles);
+                     d_items, count, total_tiles, stream_out ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -682,17 +686,18 @@ hipError_t life_tb_batch_rho(const BatchItem *d_items, int count, uint64_t total
 
 hipError_t launch_life_tb_batch(int max_rho, int threads, const BatchItem *d_items, int count,
                                 uint64_t total_tiles, int max_steps, int groups,
-                                hipStream_t stream) {
+                                bool stream_out, hipStream_t stream) {
   if (max_steps < 1 || max_steps > kMaxStepsPerPass || groups < 1) return hipErrorInvalidValue;
   const bool t512 = threads == 512;
   if (threads != 256 && threads != 512) return hipErrorInvalidValue;
+  const bool so = stream_out;
   switch (max_rho) {
-    case 64: return t512 ? life_tb_batch_rho<64, 512>(d_items, count, total_tiles, max_steps, groups, stream)
-                         : life_tb_batch_rho<64, 256>(d_items, count, total_tiles, max_steps, groups, stream);
-    case 128: return t512 ? life_tb_batch_rho<128, 512>(d_items, count, total_tiles, max_steps, groups, stream)
-                          : life_tb_batch_rho<128, 256>(d_items, count, total_tiles, max_steps, groups, stream);
-    case 256: return t512 ? life_tb_batch_rho<256, 512>(d_items, count, total_tiles, max_steps, groups, stream)
-                          : life_tb_batch_rho<256, 256>(d_items, count, total_tiles, max_steps, groups, stream);
+    case 64: return t512 ? life_tb_batch_rho<64, 512>(d_items, count, total_tiles, max_steps, groups, so, stream)
+                         : life_tb_batch_rho<64, 256>(d_items, count, total_tiles, max_steps, groups, so, stream);
+    case 128: return t512 ? life_tb_batch_rho<128, 512>(d_items, count, total_tiles, max_steps, groups, so, stream)
+                          : life_tb_batch_rho<128, 256>(d_items, count, total_tiles, max_steps, groups, so, stream);
+    case 256: return t512 ? life_tb_batch_rho<256, 512>(d_items, count, total_tiles, max_steps, groups, so, stream)
+                          : life_tb_batch_rho<256, 256>(d_items, count, total_tiles, max_steps, groups, so, stream);
     default: return hipErrorInvalidValue;
   }
 }
