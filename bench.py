@@ -261,12 +261,21 @@ def bench_sweep(torch, sg, inputs, rs, rhos, steps):
     return out
 
 
-def bench_diffusion(torch, sg, inputs, rhos, steps, warmup, reps):
+DIFF_TB_SHAPES = [(rho, T) for rho in (16, 32, 64) for T in (4, 8, 12, 16)]
+
+
+def _shape(text):
+    rho, T = text.lower().split("x")
+    return int(rho), int(T)
+
+
+def bench_diffusion(torch, sg, inputs, rhos, steps, warmup, reps, shapes=DIFF_TB_SHAPES):
     """FP32 diffusion at r = 14 (the diffusion workload's size), lambda and
     bounding box: one launch per step at each rho (`reps` samples of a tenth
     of `steps` launches), and the temporally blocked passes at rho = 16, 32
-    and 64 with 4 or 8 steps per pass (`reps` calls of `steps` steps); 8
-    algorithmic bytes per cell and step."""
+    and 64 with 4, 8, 12 or 16 steps per pass (`shapes`; `reps` calls of 48
+    steps, so every pass length divides them); 8 algorithmic bytes per cell
+    and step."""
     r = 14
     cells = 3 ** r
     u0 = inputs.uniform_field(r, SEED)
@@ -289,14 +298,20 @@ def bench_diffusion(torch, sg, inputs, rhos, steps, warmup, reps):
             del bufs
     tb = {"lambda": {}, "bbox": {}}
     Out, Work = torch.zeros_like(U), torch.zeros_like(U)
+    tb_steps = 48
     for map_kind in ("lambda", "bbox"):
-        for rho in (16, 32, 64):
-            for T in (4, 8):
-                def run():
-                    sg.sg_diffuse_steps(map_kind, r, rho, steps, U, Out, Work, 0.2, steps_per_pass=T)
-                tb[map_kind][(rho, T)] = [ms / steps for ms in time_samples(torch, run, reps, 1)]
-                log(f"diffuse r=14 {map_kind:6s} rho={rho:3d} {T}/pass: "
-                    f"{stats(tb[map_kind][(rho, T)])['median_ms'] * 1e3:8.2f} us/step")
+        for rho, T in shapes:
+            def run():
+                sg.sg_diffuse_steps(map_kind, r, rho, tb_steps, U, Out, Work, 0.2,
+                                    steps_per_pass=T)
+            try:
+                run()
+            except RuntimeError as e:  # a pass the device's LDS cannot hold
+                log(f"diffuse r=14 {map_kind:6s} rho={rho:3d} {T}/pass: not run ({e})")
+                continue
+            tb[map_kind][(rho, T)] = [ms / tb_steps for ms in time_samples(torch, run, reps, 1)]
+            log(f"diffuse r=14 {map_kind:6s} rho={rho:3d} {T:2d}/pass: "
+                f"{stats(tb[map_kind][(rho, T)])['median_ms'] * 1e3:8.2f} us/step")
     med = lambda v: stats(v)["median_ms"]  # noqa: E731
     cands = [((rho, 1), med(v)) for rho, v in res["lambda"].items()]
     cands += [(k, med(v)) for k, v in tb["lambda"].items()]
@@ -538,6 +553,9 @@ def main():
                     help="cell updates queued per scheduling round (0: one pass per round)")
     ap.add_argument("--serve-budget", type=float, default=2e9,
                     help="cell updates per batched pass, oldest requests first (0: no budget)")
+    ap.add_argument("--diffusion-shapes", nargs="*", type=_shape, default=DIFF_TB_SHAPES,
+                    help="temporally blocked diffusion passes to time, as RHOxT (default: "
+                         "rho 16, 32, 64 x 4, 8, 12, 16 steps per pass)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -745,7 +763,8 @@ def main():
         extras["sweep_one_launch_per_step"] = bench_sweep(torch, sg, inputs, (10, 12, 14),
                                                           (4, 8, 16, 32, 64, 128, 256), 100)
     if "diffusion" in legs:
-        extras["diffusion"] = bench_diffusion(torch, sg, inputs, (16, 64, 128, 256), K, W, REPS)
+        extras["diffusion"] = bench_diffusion(torch, sg, inputs, (16, 64, 128, 256), K, W, REPS,
+                                              args.diffusion_shapes)
     if "batched" in legs:
         extras["batched"] = bench_batched(torch, sg, inputs, args.batch_count, 50, REPS)
     if "fractals" in legs:
@@ -767,8 +786,8 @@ def main():
             # the diffusion workload's error against the oracle's FP64 run,
             # which is also that workload's CPU baseline
             extras["diffusion"]["error_vs_fp64"] = diffusion_error_vs_fp64(
-                torch, sg, inputs, [("lambda", 16, 1), ("lambda", 16, 8), ("lambda", 32, 8),
-                                    ("bbox", 16, 8)])
+                torch, sg, inputs, [("lambda", 16, 1), ("lambda", 16, 8), ("lambda", 16, 16),
+                                    ("lambda", 32, 8), ("bbox", 16, 8)])
 
     prop = torch.cuda.get_device_properties(0)
     wl = min(wp["lambda"], key=lambda k: med(wp["lambda"][k])) if wp["lambda"] else None

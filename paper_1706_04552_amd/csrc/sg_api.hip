@@ -287,7 +287,7 @@ SG_API int sg_diffuse_steps(int map, int r, int rho, int steps, int steps_per_pa
   if (steps < 0 || steps_per_pass < 0 || steps_per_pass > sg::kMaxDiffuseStepsPerPass)
     return SG_EINVAL;
   const bool tb_ok = sg::diffuse_tb_supported(rho);
-  if (steps_per_pass == 0) steps_per_pass = tb_ok ? sg::kMaxDiffuseStepsPerPass : 1;
+  if (steps_per_pass == 0) steps_per_pass = tb_ok ? sg::diffuse_tb_default_steps(rho) : 1;
   if (steps_per_pass > 1 && !tb_ok) return SG_EINVAL;
   if (!d_in || !d_out || misaligned(d_in) || misaligned(d_out)) return SG_EINVAL;
   const size_t bytes = ((size_t)1 << r) * ((size_t)1 << r) * sizeof(float);

@@ -70,9 +70,13 @@ hipError_t launch_compact_init(const PassArgs &a, uint64_t seed, uint64_t thresh
 hipError_t launch_life_tb_compact(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
 
 // Temporally blocked FP32 diffusion: T steps per pass, T in
-// [1, kMaxDiffuseStepsPerPass], for tile side rho = 64.
-constexpr int kMaxDiffuseStepsPerPass = 8;
+// [1, kMaxDiffuseStepsPerPass], for tile sides rho in {16, 32, 64}.
+constexpr int kMaxDiffuseStepsPerPass = 16;
 bool diffuse_tb_supported(int rho);
+// What steps_per_pass = 0 selects: the measured best pass length at this
+// tile side (16 at rho = 16, whose halo is cheap next to its setup; 8 at 32
+// and 64, where the wider region of a longer pass costs occupancy).
+int diffuse_tb_default_steps(int rho);
 hipError_t launch_diffuse_tb(const PassArgs &a, int T, const float *in, float *out,
                              float alpha);
 

@@ -241,7 +241,7 @@ def test_diffuse_steps_validation(lib):
     from paper_1706_04552_amd import sg
     a, b, w = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x7000000000), ctypes.c_void_p(0x7100000000)
     r = 8
-    assert lib.sg_diffuse_steps(0, r, 64, 10, 9, a, b, w, 0.2, None) == sg.SG_EINVAL
+    assert lib.sg_diffuse_steps(0, r, 64, 10, 17, a, b, w, 0.2, None) == sg.SG_EINVAL
     assert lib.sg_diffuse_steps(0, r, 128, 10, 4, a, b, w, 0.2, None) == sg.SG_EINVAL
     assert lib.sg_diffuse_steps(0, r, 8, 10, 4, a, b, w, 0.2, None) == sg.SG_EINVAL
     assert lib.sg_diffuse_steps(0, r, 64, -2, 4, a, b, w, 0.2, None) == sg.SG_EINVAL

@@ -229,7 +229,7 @@ def test_diffuse_step_every_cell(diffusion_ref, steps, rho, map_kind):
 
 
 @pytest.mark.parametrize("steps", [16, 500])
-@pytest.mark.parametrize("rho,T", [(16, 4), (16, 8), (32, 4), (32, 8), (64, 4), (64, 8)])
+@pytest.mark.parametrize("rho,T", [(rho, T) for rho in (16, 32, 64) for T in (4, 8, 12, 16)])
 @pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
 def test_diffuse_steps_every_cell(diffusion_ref, steps, rho, T, map_kind):
     r, u0, dpos, off, refs = diffusion_ref

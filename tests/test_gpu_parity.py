@@ -220,7 +220,9 @@ def test_diffusion_small(map_kind, r, rho):
 @pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
 @pytest.mark.parametrize("rho", [16, 32, 64])
 @pytest.mark.parametrize("r,steps,spp", [(6, 1, 8), (6, 8, 8), (7, 13, 8), (8, 30, 5), (9, 17, 3),
-                                         (10, 40, 8), (10, 0, 8), (8, 9, 1), (5, 11, 8)])
+                                         (10, 40, 8), (10, 0, 8), (8, 9, 1), (5, 11, 8),
+                                         (8, 30, 16), (9, 17, 12), (10, 40, 16), (7, 13, 11),
+                                         (6, 16, 16), (10, 33, 9), (9, 20, 0)])
 def test_diffuse_steps_equal_one_step_calls_and_oracle(map_kind, rho, r, steps, spp):
     if rho > (1 << r):
         pytest.skip("tile wider than the gasket")

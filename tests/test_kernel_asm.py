@@ -7,7 +7,7 @@ into the load's own conditional block, it has to wait for that load there
 8 % of the pass at rho = 256 when it happened.  These tests compile the passes
 to gfx950 assembly and check that no life region load is waited on inside its
 block, and that the diffusion pass issues all its region loads before its
-first wait on them (it lists its chunks meanwhile).
+first wait on them (it clears its LDS planes meanwhile).
 """
 import os
 import re
@@ -87,7 +87,7 @@ def diffuse_asm(tmp_path_factory):
 def test_diffusion_tile_pass_issues_all_region_loads_before_waiting(diffuse_asm):
     # the diffusion pass lists its chunks while every region load is in flight
     names = re.findall(r"^(_Z\w*k_diffuse_tb\w*):", diffuse_asm, re.M)
-    assert len(names) == 6  # rho 16, 32, 64 for both maps
+    assert len(names) == 12  # rho 16, 32, 64 for both maps, halo 8 and 16
     for name in names:
         start = diffuse_asm.index(name + ":")
         end = diffuse_asm.index(".Lfunc_end", start)
