@@ -128,37 +128,56 @@ constexpr int kMaskWords = (SG_FRAC_MAX_RHO + 31) / 32;
 // themselves); smaller ones a cell at a time.
 constexpr uint32_t kWordTileMin = 64;
 
-template <int M>
-__device__ __forceinline__ void build_row_masks(const FracArgs &f, int q, uint32_t rho,
-                                                uint32_t *L, uint32_t *rows) {
+// Level masks: L[j][d] (kMaskWords words) holds the tile columns whose
+// level-j digit forms a kept offset with row digit d.  A thread builds one
+// word, walking its 32 columns with a running digit (the level-j digit of
+// column c steps every m^j columns).
+template <int M, int NT = kFracThreads>
+__device__ __forceinline__ void build_level_masks(const FracArgs &f, int q, uint32_t rho,
+                                                  uint32_t *L) {
   const int nw = (int)(rho + 31) / 32;  // words a row needs
-  const int nl = q * M * nw;
-  for (int e = threadIdx.x; e < nl; e += kFracThreads) {
+  for (int e = threadIdx.x; e < q * M * nw; e += NT) {
     const int wd = e % nw, d = (e / nw) % M, j = e / (nw * M);
-    uint32_t div = 1;
-    for (int l = 0; l < j; ++l) div *= M;
+    uint32_t span = 1;  // columns per level-j digit
+    for (int l = 0; l < j; ++l) span *= M;
+    const uint32_t c0 = 32u * (uint32_t)wd;
+    uint32_t dig = (c0 / span) % M, rem = c0 % span;
+    const int bits = (int)rho - (int)c0 < 32 ? (int)rho - (int)c0 : 32;
     uint32_t w = 0;
-    const int bits = (int)rho - 32 * wd < 32 ? (int)rho - 32 * wd : 32;
     for (int b = 0; b < bits; ++b) {
-      const uint32_t dx = ((32u * wd + b) / div) % M;
-      w |= ((f.kept >> (dx + M * d)) & 1u) << b;
+      w |= ((f.kept >> (dig + M * d)) & 1u) << b;
+      if (++rem == span) {
+        rem = 0;
+        dig = dig + 1 == (uint32_t)M ? 0u : dig + 1;
+      }
     }
     L[(j * M + d) * kMaskWords + wd] = w;
   }
+}
+
+// Membership bits of tile row ty, word wd: the AND over levels j of
+// L[j][digit_j(ty)].
+template <int M>
+__device__ __forceinline__ uint32_t row_mask_word(const uint32_t *L, int q, uint32_t ty,
+                                                  uint32_t wd) {
+  uint32_t w = ~0u, v = ty;
+  for (int j = 0; j < q; ++j) {
+    const uint32_t d = v % M;
+    v /= M;
+    w &= L[(j * M + d) * kMaskWords + wd];
+  }
+  return w;
+}
+
+template <int M>
+__device__ __forceinline__ void build_row_masks(const FracArgs &f, int q, uint32_t rho,
+                                                uint32_t *L, uint32_t *rows) {
+  const int nw = (int)(rho + 31) / 32;
+  build_level_masks<M>(f, q, rho, L);
   __syncthreads();
   for (int e = threadIdx.x; e < (int)rho * kMaskWords; e += kFracThreads) {
     const uint32_t ty = e / kMaskWords, wd = e - ty * kMaskWords;
-    if ((int)wd >= nw) {
-      rows[e] = 0u;
-      continue;
-    }
-    uint32_t w = ~0u, v = ty;
-    for (int j = 0; j < q; ++j) {
-      const uint32_t d = v % M;
-      v /= M;
-      w &= L[(j * M + d) * kMaskWords + wd];
-    }
-    rows[e] = w;
+    rows[e] = (int)wd < nw ? row_mask_word<M>(L, q, ty, wd) : 0u;
   }
 }
 
@@ -292,26 +311,43 @@ __global__ __launch_bounds__(kFracThreads) void k_frac_life(FracArgs f, FracPass
 }
 
 // Life step on tiles of kWordTileMin cells a side or more (one tile per
-// workgroup): the tile and a one-cell halo are staged in LDS with every tile
-// row starting on a 4-byte boundary, then one thread takes 4 cells of a tile
-// row at a time as one LDS word (SWAR on bytes: 3-row column sums, neighbour
-// bytes by funnel shifts, B3/S23 as (count | self) == 3), masks them with the
-// in-tile membership bits and stores them.
-template <int M>
-__host__ __device__ constexpr uint32_t life_stride(uint32_t rho) {
-  return 4u + 4u * ((rho + 1u + 3u) / 4u) + 4u;  // left pad word, tile + right halo, one spare word
+// workgroup).  The tile and a one-cell halo are staged in LDS as rows of
+// words, word k of a row holding tile columns 4k - 4 .. 4k - 1.  Rows of the
+// embedding (n = m^r bytes) start at every alignment mod 4, so a region row
+// is read as 4-byte-aligned words, lane k of a row's lane group holding the
+// k-th one and taking the next lane's through a wave shift to realign them
+// (tiles at the grid's edge read bytes, with bounds checks).  Then lane k of
+// an output row's lane group takes tile columns 4k .. 4k + 3 as one word
+// from three LDS rows (SWAR on bytes: 3-row column sums, neighbour bytes by
+// funnel shifts, B3/S23 as (count | self) == 3), masks them with the in-tile
+// membership bits and realigns the results the other way into aligned output
+// words: whole words inside the tile are one store, the words at its two
+// ends are written byte by byte.
+__host__ __device__ constexpr uint32_t life_row_words(uint32_t rho) {
+  return (rho + 3u) / 4u + 2u;  // tile words + a halo word each side
 }
 
-template <int M, bool LAMBDA>
-__global__ __launch_bounds__(kFracThreads) void k_frac_life_words(FracArgs f, FracPass p,
+static_assert(life_row_words(SG_FRAC_MAX_RHO) + 1 <= 64, "a region row's lane group fits a wave");
+
+__device__ __forceinline__ uint32_t lane_next(uint32_t v) {  // lane i <- lane i + 1
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint32_t lane_prev(uint32_t v) {  // lane i <- lane i - 1
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xf, 0xf, true);
+}
+
+template <int M, bool LAMBDA, int NT>
+__global__ __launch_bounds__(NT) void k_frac_life_words(FracArgs f, FracPass p,
                                                                   uint64_t tile_base,
                                                                   const uint8_t *__restrict__ in,
                                                                   uint8_t *__restrict__ out) {
-  extern __shared__ __align__(16) uint8_t reg[];  // (rho + 2) rows of life_stride bytes
+  extern __shared__ __align__(16) uint32_t regw[];  // rho + 2 rows of life_row_words words
   __shared__ uint32_t L[160];
   __shared__ uint32_t tile_xy[2];
   __shared__ uint8_t tile_ok;
+  constexpr int NW = NT / 64;  // waves per workgroup
   const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = __lane_id();
   const uint64_t t = tile_base + logical_group();
   if (tid == 0) {
     uint32_t bx = 0, by = 0;
@@ -319,68 +355,118 @@ __global__ __launch_bounds__(kFracThreads) void k_frac_life_words(FracArgs f, Fr
     tile_xy[0] = bx;
     tile_xy[1] = by;
   }
-  // level masks (the row masks are formed per word below)
-  const int nw = (int)(p.rho + 31) / 32;
-  for (int e = tid; e < p.q * M * nw; e += kFracThreads) {
-    const int wd = e % nw, d = (e / nw) % M, j = e / (nw * M);
-    uint32_t div = 1;
-    for (int l = 0; l < j; ++l) div *= M;
-    uint32_t w = 0;
-    const int bits = (int)p.rho - 32 * wd < 32 ? (int)p.rho - 32 * wd : 32;
-    for (int b = 0; b < bits; ++b) w |= ((f.kept >> (((32u * wd + b) / div) % M + M * d)) & 1u) << b;
-    L[(j * M + d) * kMaskWords + wd] = w;
-  }
+  build_level_masks<M, NT>(f, p.q, p.rho, L);
   __syncthreads();
   if (!tile_ok) return;
-  const uint32_t S = life_stride<M>(p.rho), side = p.rho + 2;
-  const int64_t X0 = (int64_t)tile_xy[0] * p.rho, Y0 = (int64_t)tile_xy[1] * p.rho;
-  // region cell (i, j), j = tile column + 1, at byte i * S + 3 + j
-  for (uint32_t e = tid; e < side * S / 4; e += kFracThreads) reinterpret_cast<uint32_t *>(reg)[e] = 0u;
-  __syncthreads();
-  for (uint32_t e = tid; e < side * side; e += kFracThreads) {
-    const uint32_t i = e / side, j = e - i * side;
-    const int64_t y = Y0 + i - 1, x = X0 + j - 1;
-    if (y >= 0 && y < p.n && x >= 0 && x < p.n) {
-      const uint8_t v = in[(size_t)y * p.n + (size_t)x];
-      if (v) reg[i * S + 3 + j] = v;
+  const uint32_t rho = p.rho, n = p.n;
+  const uint32_t SW = life_row_words(rho), wpr = (rho + 3u) / 4u;
+  const int64_t X0 = (int64_t)tile_xy[0] * rho, Y0 = (int64_t)tile_xy[1] * rho;
+
+  // 1. stage region rows i = 0 .. rho + 1 (y = Y0 - 1 + i): lane group g of
+  //    a wave takes rows, lane k of it LDS word k (the group's last lane only
+  //    supplies its aligned word to the one before it)
+  {
+    const uint32_t GL = SW + 1u, GPW = 64u / GL;  // lanes per group, groups per wave
+    const uint32_t g = (uint32_t)lane / GL, k = (uint32_t)lane - g * GL;
+    const bool interior = X0 >= 8 && X0 + 4 * (int64_t)SW + 4 <= (int64_t)n && Y0 >= 1 &&
+                          Y0 + rho + 1 <= (int64_t)n;
+    const uint32_t rows_per_round = GPW * NW;
+    if (interior) {
+      // kBatch rows per lane in flight at once: their aligned words loaded
+      // first, then realigned (wave shift + funnel shift) and stored
+      constexpr int kBatch = 8;
+      for (uint32_t i0 = 0; i0 < rho + 2u; i0 += kBatch * rows_per_round) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const uint32_t i = i0 + (uint32_t)u * rows_per_round + (uint32_t)wave * GPW + g;
+          const bool mine = g < GPW && i < rho + 2u;
+          // aligned word k of the row from the byte of tile column -4 on
+          const uint64_t base = (uint64_t)(Y0 - 1 + (int64_t)i) * n + (uint64_t)(X0 - 4);
+          v[u] = mine ? *reinterpret_cast<const uint32_t *>(in + (base & ~3ull) + 4ull * k) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+          const uint32_t i = i0 + (uint32_t)u * rows_per_round + (uint32_t)wave * GPW + g;
+          const bool mine = g < GPW && i < rho + 2u;
+          const uint64_t base = (uint64_t)(Y0 - 1 + (int64_t)i) * n + (uint64_t)(X0 - 4);
+          const uint32_t word =
+              __builtin_amdgcn_alignbit(lane_next(v[u]), v[u], (uint32_t)(base & 3u) * 8u);
+          if (mine && k < SW) regw[i * SW + k] = word;
+        }
+      }
+    } else {
+      for (uint32_t i0 = 0; i0 < rho + 2u; i0 += rows_per_round) {
+        const uint32_t i = i0 + (uint32_t)wave * GPW + g;
+        const int64_t y = Y0 - 1 + (int64_t)i;
+        if (!(g < GPW && i < rho + 2u && k < SW)) continue;
+        uint32_t word = 0u;
+        if (y >= 0 && y < (int64_t)n) {
+          const int64_t x0 = X0 - 4 + 4 * (int64_t)k;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int64_t x = x0 + b;
+            if (x >= 0 && x < (int64_t)n)
+              word |= (uint32_t)in[(uint64_t)y * n + (uint64_t)x] << (8 * b);
+          }
+        }
+        regw[i * SW + k] = word;
+      }
     }
   }
   __syncthreads();
-  const uint32_t wpr = (p.rho + 3) / 4;
-  for (uint32_t e = tid; e < p.rho * wpr; e += kFracThreads) {
-    const uint32_t ty = e / wpr, c = e - ty * wpr;
-    const uint32_t *r0 = reinterpret_cast<const uint32_t *>(reg + ty * S + 4) + c;  // row above
-    const uint32_t *r1 = reinterpret_cast<const uint32_t *>(reg + (ty + 1) * S + 4) + c;
-    const uint32_t *r2 = reinterpret_cast<const uint32_t *>(reg + (ty + 2) * S + 4) + c;
-    const uint32_t C = r1[0];
-    const uint32_t V = r0[0] + C + r2[0];
-    const uint32_t Vp = r0[-1] + r1[-1] + r2[-1];
-    const uint32_t Vn = r0[1] + r1[1] + r2[1];
-    const uint32_t Lb = __builtin_amdgcn_alignbit(V, Vp, 24);  // byte i <- column 4c + i - 1
-    const uint32_t Rb = __builtin_amdgcn_alignbit(Vn, V, 8);   // byte i <- column 4c + i + 1
-    const uint32_t cnt = Lb + V + Rb - C;                      // live neighbours, per byte
-    const uint32_t x = (cnt | C) ^ 0x03030303u;
-    uint32_t z = x | (x >> 1);
-    z |= z >> 2;
-    // membership of columns 4c..4c+3 of row ty: AND over levels of L[j][digit_j(ty)]
-    uint32_t m = ~0u, v = ty;
-    const uint32_t wd = (4 * c) >> 5;
-    for (int j = 0; j < p.q; ++j) {
-      const uint32_t d = v % M;
-      v /= M;
-      m &= L[(j * M + d) * kMaskWords + wd];
+
+  // 2. tile rows ty: lane k of a group takes tile columns 4k .. 4k + 3 (k <
+  //    wpr), and output word k of the row (k <= wpr)
+  const uint32_t GL = wpr + 1u, GPW = 64u / GL;
+  const uint32_t g = (uint32_t)lane / GL, k = (uint32_t)lane - g * GL;
+  const uint32_t rows_per_round = GPW * NW;
+  for (uint32_t t0 = 0; t0 < rho; t0 += rows_per_round) {
+    const uint32_t ty = t0 + (uint32_t)wave * GPW + g;
+    const bool mine = g < GPW && ty < rho;
+    uint32_t alive = 0u;
+    if (mine && k < wpr) {
+      const uint32_t *r0 = regw + ty * SW + k + 1u;  // row above; word k + 1 = columns 4k ..
+      const uint32_t *r1 = r0 + SW, *r2 = r1 + SW;
+      const uint32_t C = r1[0];
+      const uint32_t V = r0[0] + C + r2[0];
+      const uint32_t Vp = r0[-1] + r1[-1] + r2[-1];
+      const uint32_t Vn = r0[1] + r1[1] + r2[1];
+      const uint32_t Lb = __builtin_amdgcn_alignbit(V, Vp, 24);  // byte i <- column 4k + i - 1
+      const uint32_t Rb = __builtin_amdgcn_alignbit(Vn, V, 8);   // byte i <- column 4k + i + 1
+      const uint32_t cnt = Lb + V + Rb - C;                      // live neighbours, per byte
+      const uint32_t x = (cnt | C) ^ 0x03030303u;
+      uint32_t z = x | (x >> 1);
+      z |= z >> 2;
+      const uint32_t m = row_mask_word<M>(L, p.q, ty, (4u * k) >> 5);
+      const uint32_t bits = (m >> ((4u * k) & 31u)) & 15u;
+      alive = ~z & ((bits * 0x00204081u) & 0x01010101u);
     }
-    const uint32_t bits = (m >> ((4 * c) & 31u)) & 15u;
-    const uint32_t alive = ~z & ((bits * 0x00204081u) & 0x01010101u);
-    uint8_t *dst = out + (size_t)(Y0 + ty) * p.n + (size_t)(X0 + 4 * c);
-    const uint32_t ncell = p.rho - 4 * c < 4 ? p.rho - 4 * c : 4;
-    if (ncell == 4 && ((uintptr_t)dst & 3u) == 0) {
-      *reinterpret_cast<uint32_t *>(dst) = alive;
+    // output word k covers tile columns 4k - d .. 4k - d + 3, d the row's
+    // first cell's offset in its aligned word
+    const uint64_t row0 = (uint64_t)(Y0 + ty) * n + (uint64_t)X0;
+    const uint32_t d = (uint32_t)(row0 & 3u);
+    const uint32_t before = lane_prev(alive);  // all lanes
+    if (!mine) continue;
+    const uint32_t w = d == 0u ? alive : __builtin_amdgcn_alignbit(alive, before, 32u - 8u * d);
+    const int tx0 = 4 * (int)k - (int)d;
+    uint8_t *dst = out + (row0 & ~3ull) + 4ull * k;
+    if (tx0 >= 0 && tx0 + 4 <= (int)rho) {
+      *reinterpret_cast<uint32_t *>(dst) = w;
     } else {
-      for (uint32_t b = 0; b < ncell; ++b) dst[b] = (uint8_t)(alive >> (8 * b));
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (tx0 + b >= 0 && tx0 + b < (int)rho) dst[b] = (uint8_t)(w >> (8 * b));
     }
   }
 }
+
+// Life tiles this wide run 512 threads: their region (about 62 KB of LDS at
+// rho = 243) leaves room for two workgroups per CU.
+#ifndef SG_FRAC_WIDE_LIFE_TILE
+#define SG_FRAC_WIDE_LIFE_TILE 128
+#endif
+constexpr uint32_t kWideLifeTile = SG_FRAC_WIDE_LIFE_TILE;
 
 constexpr uint64_t kFracMaxGroups = 1ull << 22;
 
@@ -390,13 +476,16 @@ hipError_t frac_pass_m(const FracArgs &f, const FracPass &p, hipStream_t s, uint
   const uint64_t groups = (p.ntiles + p.tpg - 1) / p.tpg;
   const bool words = p.rho >= kWordTileMin;
   const size_t lds = !LIFE ? 0
-                     : words ? (size_t)(p.rho + 2) * life_stride<M>(p.rho)
+                     : words ? (size_t)(p.rho + 2) * life_row_words(p.rho) * sizeof(uint32_t)
                              : (size_t)p.tpg * (p.rho + 2) * (p.rho + 2);
   for (uint64_t g0 = 0; g0 < groups; g0 += kFracMaxGroups) {
     const uint64_t g = groups - g0 < kFracMaxGroups ? groups - g0 : kFracMaxGroups;
-    if (LIFE && words)
-      hipLaunchKernelGGL((k_frac_life_words<M, LAMBDA>), dim3((unsigned)g), dim3(kFracThreads),
-                         lds, s, f, p, g0 * (uint64_t)p.tpg, in, a);
+    if (LIFE && words && p.rho >= kWideLifeTile)
+      hipLaunchKernelGGL((k_frac_life_words<M, LAMBDA, 2 * kFracThreads>), dim3((unsigned)g),
+                         dim3(2 * kFracThreads), lds, s, f, p, g0 * (uint64_t)p.tpg, in, a);
+    else if (LIFE && words)
+      hipLaunchKernelGGL((k_frac_life_words<M, LAMBDA, kFracThreads>), dim3((unsigned)g),
+                         dim3(kFracThreads), lds, s, f, p, g0 * (uint64_t)p.tpg, in, a);
     else if (LIFE)
       hipLaunchKernelGGL((k_frac_life<M, LAMBDA>), dim3((unsigned)g), dim3(kFracThreads), lds, s,
                          f, p, g0 * (uint64_t)p.tpg, in, a);

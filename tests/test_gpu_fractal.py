@@ -14,7 +14,9 @@ from paper_1706_04552_amd import inputs, sg
 
 pytestmark = pytest.mark.gpu
 
-ORACLE = {"carpet": O.CARPET, "vicsek": O.VICSEK, "gasket": O.GASKET}
+# an m = 4 motif: 7 of the 16 sub-squares
+QUAD = O.Fractal(4, [(0, 0), (3, 0), (1, 1), (1, 2), (2, 2), (0, 3), (3, 3)])
+ORACLE = {"carpet": O.CARPET, "vicsek": O.VICSEK, "gasket": O.GASKET, "quad": QUAD}
 
 
 def note(msg):
@@ -89,6 +91,20 @@ def test_frac_life_exact(map_kind, name, r, rho):
     note(f"frac_life {map_kind} {name} r={r} rho={rho} 6 steps")
     of = ORACLE[name]
     a0 = inputs.fractal_state(of.m, of.offsets, r, 0.5, 40 + r)
+    got = gpu_frac_life(lib_fractal(name), map_kind, r, rho, a0, 6).cpu().numpy()
+    assert np.array_equal(got, O.frac_life_steps(of, r, a0, 6))
+
+
+@pytest.mark.parametrize("map_kind", ["lambda", "bbox"])
+@pytest.mark.parametrize("name,r,rho", [("carpet", 6, 81), ("carpet", 6, 243), ("carpet", 7, 243),
+                                        ("vicsek", 7, 81), ("vicsek", 7, 243), ("gasket", 10, 64),
+                                        ("gasket", 10, 128), ("quad", 5, 64), ("quad", 4, 64)])
+def test_frac_life_exact_word_tiles(map_kind, name, r, rho):
+    # tiles of 64 cells a side or more, at sizes with tiles off the grid's
+    # edge (the aligned-word staging) as well as on it (the byte staging)
+    note(f"frac_life word tiles {map_kind} {name} r={r} rho={rho} 6 steps")
+    of = ORACLE[name]
+    a0 = inputs.fractal_state(of.m, of.offsets, r, 0.5, 90 + r)
     got = gpu_frac_life(lib_fractal(name), map_kind, r, rho, a0, 6).cpu().numpy()
     assert np.array_equal(got, O.frac_life_steps(of, r, a0, 6))
 
