@@ -37,6 +37,7 @@
 // cannot reach the tile in the steps left.  Rows 0 and R - 1 of the region
 // are T cells from the tile, so no updated chunk reads outside the plane.
 #include <atomic>
+#include <type_traits>
 
 #include "sg_device.h"
 #include "sg_launch.h"
@@ -53,6 +54,11 @@ template <int RHO, int H>
 struct DtGeom {
   static constexpr int CW = RHO + 2 * H;  // region columns = plane pitch (floats)
   static constexpr int CC = CW / 4;       // region chunks per row
+  // plane stride (floats): the largest region's rows, so the second plane is
+  // a fixed offset from the first and every LDS access of a step is a base
+  // register plus an immediate
+  static constexpr int PLANE = (RHO + 2 * H) * CW;
+  static_assert(PLANE * 4 + (2 * CW + 4) * 4 < 65536, "LDS offsets fit their 16-bit field");
   static constexpr int NT = RHO >= 64 ? 512 : 256;
   // chunks of the largest region (T = H)
   static constexpr int SLOTS = (RHO + 2 * H) * CC;
@@ -170,7 +176,8 @@ __constant__ DtTable kDtTable = DtTableOf<RHO, H>::table;
 template <int RHO, int H>
 size_t dt_lds_bytes(int T) {
   using G = DtGeom<RHO, H>;
-  return sizeof(float) * 2 * (size_t)(RHO + 2 * T) * G::CW + sizeof(uint32_t) * DtTableOf<RHO, H>::n;
+  return sizeof(float) * ((size_t)G::PLANE + (size_t)(RHO + 2 * T) * G::CW) +
+         sizeof(uint32_t) * DtTableOf<RHO, H>::n;
 }
 
 // Lane i receives lane i - 1's (wave_shr:1) or lane i + 1's (wave_shl:1)
@@ -227,8 +234,8 @@ __global__ __launch_bounds__((DtGeom<RHO, H>::NT)) void k_diffuse_tb(const float
   const int nslots = R * G::CC;
   // region cell (i, x) of a plane is at i * CW + x
   float *plane0 = flds;
-  float *plane1 = flds + R * G::CW;
-  uint32_t *list = reinterpret_cast<uint32_t *>(flds + 2 * R * G::CW);
+  float *plane1 = flds + G::PLANE;
+  uint32_t *list = reinterpret_cast<uint32_t *>(plane1 + R * G::CW);
 
   // the 3 x 3 blocks around the tile that hold gasket cells: bit b =
   // (dbx + 1) + 3 (dby + 1), lane b testing block b
@@ -254,7 +261,7 @@ __global__ __launch_bounds__((DtGeom<RHO, H>::NT)) void k_diffuse_tb(const float
   }
   {
     float4 *z = reinterpret_cast<float4 *>(flds);
-    for (int e = tid; e < 2 * nslots; e += NT) z[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int e = tid; e < G::PLANE / 4 + nslots; e += NT) z[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
   if (tid == 0) nchunk = 0u;
   __syncthreads();
@@ -334,21 +341,23 @@ __global__ __launch_bounds__((DtGeom<RHO, H>::NT)) void k_diffuse_tb(const float
   for (int kk = 0; kk < KE; ++kk)
     cur[kk] = kk < kheld && steps_live[kk] > 0 ? *reinterpret_cast<const float4 *>(plane0 + off[kk])
                                  : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  for (int s = 0; s < T; ++s) {
-    const float *src = (s & 1) ? plane1 : plane0;
-    float *dst = (s & 1) ? plane0 : plane1;
+  // One step from the plane at float offset SRC to the one at DST (0 or
+  // PLANE): every access is relative to the chunk's north neighbour in
+  // plane 0, so its address is one register plus an immediate.
+  auto step = [&](int s, auto src_off, auto dst_off) {
+    constexpr int SRC = decltype(src_off)::value, DST = decltype(dst_off)::value;
 #pragma unroll
     for (int kk = 0; kk < KE; ++kk) {
       if (kk >= kheld) break;  // no thread holds a chunk here
       // the neighbouring lanes' cells, before any lane leaves
       const float wlane = prev_lane(cur[kk].w), elane = next_lane(cur[kk].x);
       if (s >= steps_live[kk]) continue;  // cannot reach the tile any more
-      const float *p = src + off[kk];
-      const float4 N = *reinterpret_cast<const float4 *>(p - G::CW);
-      const float4 S = *reinterpret_cast<const float4 *>(p + G::CW);
+      float *q = plane0 + off[kk] - G::CW;  // the north neighbour in plane 0
+      const float4 N = *reinterpret_cast<const float4 *>(q + SRC);
+      const float4 S = *reinterpret_cast<const float4 *>(q + SRC + 2 * G::CW);
       float Wn = (nb[kk] & 1u) ? wlane : 0.0f, En = (nb[kk] & 4u) ? elane : 0.0f;
-      if (nb[kk] & 2u) Wn = p[-1];
-      if (nb[kk] & 8u) En = p[4];
+      if (nb[kk] & 2u) Wn = q[SRC + G::CW - 1];
+      if (nb[kk] & 8u) En = q[SRC + G::CW + 4];
       const float cu[4] = {cur[kk].x, cur[kk].y, cur[kk].z, cur[kk].w};
       const float nu[4] = {N.x, N.y, N.z, N.w}, su[4] = {S.x, S.y, S.z, S.w};
       float o[4];
@@ -360,10 +369,18 @@ __global__ __launch_bounds__((DtGeom<RHO, H>::NT)) void k_diffuse_tb(const float
                               __builtin_fmaf(-deg[kk][j], cu[j], (w + ee) + (nu[j] + su[j])), cu[j]);
       }
       cur[kk] = make_float4(o[0], o[1], o[2], o[3]);
-      *reinterpret_cast<float4 *>(dst + off[kk]) = cur[kk];
+      *reinterpret_cast<float4 *>(q + DST + G::CW) = cur[kk];
     }
     __syncthreads();
+  };
+  using Zero = std::integral_constant<int, 0>;
+  using Second = std::integral_constant<int, G::PLANE>;
+  int s = 0;
+  for (; s + 1 < T; s += 2) {
+    step(s, Zero{}, Second{});
+    step(s + 1, Second{}, Zero{});
   }
+  if (s < T) step(s, Zero{}, Second{});
   const float *fin = (T & 1) ? plane1 : plane0;
 
   // 4. store the tile, whole 64-byte granules (16 floats)
