@@ -7,6 +7,11 @@ Every case is compared cell by cell: life bit-exact against the oracle;
 diffusion bit-exact against one launch per step (the same FP32 arithmetic)
 and within 1e-5 (max-abs relative to the field's scale, and relative L2) of
 the FP64 oracle, with every cell off the gasket exactly 0.
+
+Embedded fractals with random motifs (m in {2, 3, 4}, a random set of kept
+sub-squares listed in a random order): the generalised block map, the write
+pass and life steps, bit-exact against the oracle, at random levels and
+block sides, both maps.
 """
 import sys
 
@@ -105,3 +110,50 @@ def test_diffuse_steps_random_sweep(case):
     assert float(np.abs(got - ref).max()) <= DIFF_RTOL * scale
     assert float(np.linalg.norm(got - ref)) <= DIFF_RTOL * max(float(np.linalg.norm(ref)), 1e-30)
     assert np.all(got[ref == 0.0] == 0.0)
+
+
+def _fractal_cases(count=60, seed=29):
+    rng = np.random.default_rng(seed)
+    out = []
+    max_r = {2: 11, 3: 7, 4: 5}  # n up to 2048, 2187, 1024
+    while len(out) < count:
+        m = int(rng.choice([2, 3, 4]))
+        k = int(rng.integers(1, min(m * m, 16) + 1))
+        cells = rng.permutation(m * m)[:k]
+        offsets = [(int(c % m), int(c // m)) for c in cells]
+        r = int(rng.integers(0, max_r[m] + 1))
+        qs = [q for q in range(r + 1) if m ** q <= 243]
+        q = int(rng.choice(qs))
+        map_kind = "lambda" if rng.random() < 0.5 else "bbox"
+        steps = int(rng.integers(1, 7))
+        out.append((m, tuple(offsets), r, m ** q, map_kind, steps, int(rng.integers(1 << 30))))
+    return out
+
+
+@pytest.mark.parametrize("case", _fractal_cases(),
+                         ids=lambda c: f"m{c[0]}-k{len(c[1])}-r{c[2]}-rho{c[3]}-{c[4]}")
+def test_fractal_random_motifs(case):
+    m, offsets, r, rho, map_kind, steps, seed = case
+    note(f"fractal m={m} offsets={offsets} r={r} rho={rho} {map_kind} {steps} steps seed={seed}")
+    of = O.Fractal(m, offsets)
+    f = sg.fractal(m, offsets)
+    n = m ** r
+    q = round(np.log(rho) / np.log(m))
+    # the generalised map (lambda's canonical table)
+    ref_map = O.frac_map(of, r - q).astype(np.int64)
+    got_map = torch.zeros(2 * len(ref_map), dtype=torch.int32, device="cuda")
+    sg.sg_frac_map(f, r, rho, got_map)
+    # the write pass
+    a = torch.zeros((n, n), dtype=torch.uint8, device="cuda")
+    sg.sg_frac_write(f, map_kind, r, rho, a, 5)
+    # life steps
+    s0 = inputs.fractal_state(m, offsets, r, 0.5, seed)
+    x = torch.from_numpy(s0).cuda()
+    y = torch.zeros_like(x)
+    for _ in range(steps):
+        sg.sg_frac_life_step(f, map_kind, r, rho, x, y)
+        x, y = y, x
+    torch.cuda.synchronize()
+    assert np.array_equal(got_map.cpu().numpy().reshape(-1, 2).astype(np.int64), ref_map)
+    assert np.array_equal(a.cpu().numpy(), O.frac_write(of, r, 5))
+    assert np.array_equal(x.cpu().numpy(), O.frac_life_steps(of, r, s0, steps))
