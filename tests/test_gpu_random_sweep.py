@@ -8,6 +8,11 @@ diffusion bit-exact against one launch per step (the same FP32 arithmetic)
 and within 1e-5 (max-abs relative to the field's scale, and relative L2) of
 the FP64 oracle, with every cell off the gasket exactly 0.
 
+Batches of gaskets (sg_batch_*) with random launch shapes (tile side,
+generations per pass, workgroups per compute unit, threads), item counts,
+levels and step counts (0 included), run with and without the hipGraph:
+every gasket bit-exact against the oracle.
+
 Embedded fractals with random motifs (m in {2, 3, 4}, a random set of kept
 sub-squares listed in a random order): the generalised block map, the write
 pass and life steps, bit-exact against the oracle, at random levels and
@@ -20,6 +25,7 @@ import pytest
 import torch
 
 import oracle as O
+from paper_1706_04552_amd import batch as B
 from paper_1706_04552_amd import inputs, sg
 
 pytestmark = pytest.mark.gpu
@@ -157,3 +163,36 @@ def test_fractal_random_motifs(case):
     assert np.array_equal(got_map.cpu().numpy().reshape(-1, 2).astype(np.int64), ref_map)
     assert np.array_equal(a.cpu().numpy(), O.frac_write(of, r, 5))
     assert np.array_equal(x.cpu().numpy(), O.frac_life_steps(of, r, s0, steps))
+
+
+def _batch_cases(count=16, seed=31):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        tune = (int(rng.choice([64, 128, 256])), int(rng.integers(1, 33)),
+                int(rng.choice([0, 1, 2, 4, 8])), int(rng.choice([256, 512])))
+        out.append((tune, int(rng.integers(1, 25)), bool(rng.random() < 0.5),
+                    int(rng.integers(1 << 30))))
+    return out
+
+
+@pytest.mark.parametrize("case", _batch_cases(),
+                         ids=lambda c: f"rho{c[0][0]}-T{c[0][1]}-g{c[0][2]}-t{c[0][3]}-n{c[1]}")
+def test_batch_random_shapes(case):
+    tune, count, graph, seed = case
+    note(f"batch tune={tune} count={count} graph={graph} seed={seed}")
+    rng = np.random.default_rng(seed)
+    hosts, gs = [], []
+    for i in range(count):
+        r = int(rng.integers(6, 12))
+        steps = int(rng.integers(0, 41))
+        a0 = inputs.bernoulli_state(r, float(rng.uniform(0.1, 0.9)), seed + i)
+        inp = torch.from_numpy(a0).cuda()
+        gs.append(B.Gasket(r, steps, inp, torch.zeros_like(inp), torch.zeros_like(inp)))
+        hosts.append(a0)
+    with B.Batch(gs, B.make_tune(*tune)) as bt:
+        bt.run(graph=graph)
+        torch.cuda.synchronize()
+    for g, a0 in zip(gs, hosts):
+        ref = a0 if g.steps == 0 else O.life_steps_sparse(g.r, a0, g.steps)
+        assert np.array_equal(g.out.cpu().numpy(), ref), (g.r, g.steps)
