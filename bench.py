@@ -745,6 +745,10 @@ def main():
         "effective_hbm_frac": round(frac_bytes, 4),
         "measured_hbm_frac": (round(traffic / (launch_us * 1e-6) / (PEAK_HBM_GBS * 1e9), 4)
                               if traffic else None),
+        # measured HBM bytes of a launch over the fractal bytes it must move
+        # (every gasket cell read once and written once)
+        "traffic_over_fractal_bytes": (round(traffic / (CA_BYTES_PER_CELL * cells), 3)
+                                       if traffic else None),
         "profile": (f"profiles/{tag}.json" if prof else None)})
     if prof:
         for key in ("valu_busy", "lds_bank_conflict_share", "avg_duration_us"):
