@@ -33,6 +33,10 @@ PEAK_ALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # functions), the gasket mask (one AND): 13 lane ops per 32 cells
 LIFE_OPS_PER_CELL = 13 / 32
 CA_BYTES_PER_CELL = 2          # read own state once, write it once
+# FP32 work of a diffusion step per gasket cell: (W + E) + (N + S) (three
+# adds), - deg * u + that (one fma), u + alpha * t (one fma): 7 flops
+DIFF_FLOPS_PER_CELL = 7
+PEAK_FP32_TFLOPS = 157.3        # MI355X vector FP32, published
 WRITE_BYTES_PER_CELL = 1       # store the constant once
 RHOS = (4, 8, 16, 32, 64, 128, 256)
 TB_RHOS = (32, 64, 128, 256)
@@ -329,7 +333,30 @@ def bench_diffusion(torch, sg, inputs, rhos, steps, warmup, reps, shapes=DIFF_TB
                           "us_per_step": round(bb_ms * 1e3, 3)},
             "cells_per_s": cells / (ms * 1e-3),
             "best_vs_best_bbox": round(bb_ms / ms, 3),
-            "effective_hbm_frac": round(8 * cells / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+            "effective_hbm_frac": round(8 * cells / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+            "roofline": diffusion_roofline(cells, best, best_T, ms)}
+
+
+def diffusion_roofline(cells, rho, T, ms_per_step):
+    """The best diffusion shape against the vector FP32 peak: the temporally
+    blocked passes are bound by VALU issue on chip (their committed profile's
+    busy share), so algorithmic flops per second is the achieved figure; the
+    profile's counter bytes give the measured HBM traffic per launch."""
+    flops = DIFF_FLOPS_PER_CELL * cells / (ms_per_step * 1e-3) / 1e12
+    out = {"kernel": f"k_diffuse_tb<{rho}, lambda>" if T > 1 else f"one launch per step, rho={rho}",
+           "bound": "alu" if T > 1 else "hbm",
+           "achieved": round(flops, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(flops / PEAK_FP32_TFLOPS, 4),
+           "flops_per_cell_step": DIFF_FLOPS_PER_CELL, "traffic": None}
+    prof = kernel_profile(f"diffuse_tb_rho{rho}_T{T}_r14") if T > 1 else None
+    if prof:
+        out["traffic"] = prof.get("bytes_per_launch")
+        out["profile"] = f"profiles/diffuse_tb_rho{rho}_T{T}_r14.json"
+        for key in ("valu_busy", "lds_bank_conflict_share", "avg_duration_us",
+                    "issued_lane_ops_per_cell_generation"):
+            if key in prof:
+                out[f"profile_{key}"] = prof[key]
+    return out
 
 
 def bench_batched(torch, sg, inputs, count, steps, runs):
