@@ -743,7 +743,14 @@ def main():
     gens_per_launch = K / launches
     launch_us = best_ms * K / launches * 1e3
     if best_T > 1:
-        kname = f"k_life_tb<{best_rho}, lambda>" if best_rho >= 32 else f"k_life_tbs<{best_rho}, lambda>"
+        if best_rho < 32:
+            kname = f"k_life_tbs<{best_rho}, lambda>"
+        elif launches == 1:
+            kname = f"k_life_tb<{best_rho}, lambda>"
+        else:
+            # the state between launches is bit-packed tiles
+            kname = (f"k_life_tb_bits<{best_rho}, lambda> (bytes to bits, "
+                     f"{launches - 2} x bits to bits, bits to bytes)")
         tag = (f"life_tb_rho{best_rho}_T{K // launches}_r{R}" if K % launches == 0 else None)
     else:
         kname = f"k_life_strip<{best_rho}, lambda>" if best_rho >= 32 else f"k_life<{best_rho}, lambda>"

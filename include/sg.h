@@ -150,7 +150,11 @@ SG_API int sg_ca_step(int map, int r, int rho, const uint8_t *d_in,
  *   d_in: read only.  d_out: receives the state after `steps` generations.
  *   d_work: a third n * n buffer used when more than one pass runs (may be
  *     NULL otherwise).  All three: device, 16-byte aligned, pairwise
- *     non-overlapping, 0 on every cell off the gasket.
+ *     non-overlapping, 0 on every cell off the gasket.  With rho in {32, 64,
+ *     128, 256} and steps_per_pass >= 2, the state between passes is kept in
+ *     d_work as bit-packed tiles (one bit per cell, lambda order), so a pass
+ *     that neither starts nor ends the run reads and writes about an eighth
+ *     of the bytes; d_work's contents after the call are unspecified.
  *   steps = 0 copies d_in to d_out.
  * Errors: SG_EINVAL (bad sizes, steps < 0, unsupported steps_per_pass for
  * rho, d_work missing when needed), SG_EALIAS, SG_EHIP. */

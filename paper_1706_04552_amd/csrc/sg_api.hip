@@ -209,6 +209,21 @@ SG_API int sg_ca_steps(int map, int r, int rho, int steps, int steps_per_pass,
   SG_INJECT();
   if (steps == 0)
     return hip_status(hipMemcpyAsync(d_out, d_in, bytes, hipMemcpyDeviceToDevice, a.stream));
+  if (tb_ok && steps_per_pass > 1 && passes >= 2) {
+    // between passes the state is bit-packed tiles, two of them in d_work
+    // (each at most n^2 / 8 bytes): bytes in, bits, ..., bits, bytes out
+    const size_t half = (sg::life_tb_bit_state_bytes(a) + 255) & ~(size_t)255;
+    void *bits[2] = {d_work, d_work + half};
+    for (int k = 1; k <= passes; ++k) {
+      const int T = pass_steps(steps, passes, k);
+      const bool first = k == 1, last = k == passes;
+      const void *src = first ? static_cast<const void *>(d_in) : bits[k % 2];
+      void *dst = last ? static_cast<void *>(d_out) : bits[(k + 1) % 2];
+      const hipError_t e = sg::launch_life_tb_bits(a, T, src, !first, dst, !last);
+      if (e != hipSuccess) return hip_status(e);
+    }
+    return SG_OK;
+  }
   // the last pass must land in d_out: alternate d_out / d_work backwards
   const uint8_t *src = d_in;
   for (int k = 1; k <= passes; ++k) {

@@ -56,6 +56,14 @@ constexpr int kDefaultStepsPerPass = 32;  // what steps_per_pass = 0 selects
 bool life_tb_supported(int rho);
 bool life_tb_dense_supported(int rho);
 hipError_t launch_life_tb(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
+// The dense pass with bit-packed tiles (one bit per cell, 3^rb tiles in
+// lambda order, rho^2 / 32 words each, 16-byte aligned) as its input
+// (in_bits) and/or its output (out_bits), the byte embedding on the other
+// side: the state between the passes of a multi-pass run.  Bytes of one
+// such state (0 for an unsupported rho):
+size_t life_tb_bit_state_bytes(const PassArgs &a);
+hipError_t launch_life_tb_bits(const PassArgs &a, int T, const void *in, bool in_bits, void *out,
+                               bool out_bits);
 // The same for tiles of side 16 (byte planes, one 16-cell chunk of halo):
 // T in [1, kMaxSmallTileSteps].
 constexpr int kMaxSmallTileSteps = 16;

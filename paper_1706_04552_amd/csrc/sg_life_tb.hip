@@ -210,6 +210,21 @@ struct TileUnitTable {
 template <int RHO>
 __constant__ TileUnits kTileUnits = TileUnitTable<RHO>::units;
 
+// The omegas (lambda_encode) of the 3 x 3 blocks around block (tbx, tby),
+// -1 for a block off the grid or off the gasket: threads 0..8 write
+// nbr[3 (dy + 1) + dx + 1]; the caller synchronises before reading them.
+__device__ __forceinline__ void neighbour_omegas(int tid, uint32_t tbx, uint32_t tby, int rb,
+                                                 int32_t *nbr) {
+  if (tid < 9) {
+    const int x = (int)tbx + tid % 3 - 1, y = (int)tby + tid / 3 - 1;
+    const int nb = 1 << rb;
+    int32_t w = -1;
+    if (x >= 0 && y >= 0 && x < nb && y < nb && (x & y) == 0)
+      w = (int32_t)lambda_encode((uint32_t)x, (uint32_t)y, rb);
+    nbr[tid] = w;
+  }
+}
+
 // Where a tile pass reads and writes cells.
 //
 // DenseMem: the 2^lgn x 2^lgn embedding itself (row y at y << lgn; callers
@@ -219,6 +234,7 @@ struct DenseMem {
   uint8_t *out;
   int lgn;
   static constexpr bool kCompact = false;
+  static constexpr bool kBits = false;
   __device__ __forceinline__ void prepare(int, uint32_t, uint32_t, int) const {}
   __device__ __forceinline__ size_t off(int y, int x) const {
     return ((size_t)(uint32_t)y << lgn) + (uint32_t)x;
@@ -238,16 +254,10 @@ struct CompactMem {
   int32_t *nbr;
   int bx, by;
   static constexpr bool kCompact = true;
+  static constexpr bool kBits = false;
   static constexpr int K = rho_log2_const(RHO);
   __device__ __forceinline__ void prepare(int tid, uint32_t tbx, uint32_t tby, int rb) const {
-    if (tid < 9) {
-      const int x = (int)tbx + tid % 3 - 1, y = (int)tby + tid / 3 - 1;
-      const int nb = 1 << rb;
-      int32_t w = -1;
-      if (x >= 0 && y >= 0 && x < nb && y < nb && (x & y) == 0)
-        w = (int32_t)lambda_encode((uint32_t)x, (uint32_t)y, rb);
-      nbr[tid] = w;
-    }
+    neighbour_omegas(tid, tbx, tby, rb, nbr);
   }
   __device__ __forceinline__ size_t tile_off(int y, int x) const {
     const int dy = (y >> K) - by + 1, dx = (x >> K) - bx + 1;
@@ -261,6 +271,7 @@ struct CompactMem {
 // wave w holds the loads of load units w, w + NW, ... (TileUnits).
 template <int RHO, int NT>
 struct RegionLoads {
+  static constexpr bool kBits = false;
   static constexpr int NW = NT / 64;                            // waves per workgroup
   static constexpr int NU = TileUnitTable<RHO>::units.nload;   // load units
   static constexpr int UPW = (NU + NW - 1) / NW;               // load units per wave
@@ -323,16 +334,94 @@ __device__ __forceinline__ void store16(uint8_t *p, const uint4 w, bool stream) 
   }
 }
 
+// Bit-packed tiles: the state between the passes of a multi-pass run, one
+// bit per cell, so a pass that neither starts nor ends the run moves a
+// quarter of a byte state's 64-byte granules at most.  Tile omega (the
+// lambda_encode of its block) is rho^2 / 32 words at omega * rho^2 / 32; in
+// it, word column j (cells 32j .. 32j + 31 of a row, bit i = cell 32j + i)
+// is rho words at j * rho, row y at + y.  Column-major, so the west and east
+// halo words of a region (one word column of a neighbour tile) are one
+// contiguous run each, and so are the T-row halos above and below in every
+// column.  Bits of cells off the gasket are 0.
+template <int RHO>
+constexpr size_t bit_tile_words() {
+  return (size_t)RHO * RHO / 32;
+}
+
+// The region of a pass read from bit-packed tiles, in flight in registers
+// until written to the plane.  With C = ceil(T / 4) and GR = rho / 4 + 2C,
+// unit u is 4 rows of region word column u / GR: region rows from
+// 4 (u % GR) - 4C + T (those in [0, R) are kept), a 16-byte run of one tile
+// column.  Thread tid holds units tid, tid + NT, ...
+template <int RHO, int NT>
+struct BitLoads {
+  static constexpr bool kBits = true;
+  static constexpr int W = RHO / 32 + 2;                                   // region words per row
+  static constexpr int GMAX = RHO / 4 + 2 * ((kMaxStepsPerPass + 3) / 4);  // row groups at T = 32
+  static constexpr int UPT = (W * GMAX + NT - 1) / NT;                    // units per thread
+  static_assert(W * GMAX * (GMAX - 1) < (1 << 20), "div_small covers u / GR");
+  uint4 v[UPT];
+  uint32_t live;  // bit k: unit tid + k NT was loaded
+};
+
+// Region word column w and row group g of unit u (BitLoads).
+__device__ __forceinline__ void bit_unit(int u, int GR, uint32_t gr_magic, int &w, int &g) {
+  w = div_small(u, gr_magic);
+  g = u - w * GR;
+}
+
+// Issues the region loads of a pass of T generations from bit-packed tiles,
+// nbr holding the omegas of the 3 x 3 blocks around the tile (-1: no tile,
+// its cells are dead).  The region's words are those of the tile, its T rows
+// above and below, and one word column each side.
+template <int RHO, int NT>
+__device__ __forceinline__ void bits_load(const uint32_t *in, const int32_t *nbr, int T,
+                                          BitLoads<RHO, NT> &ld) {
+  using LD = BitLoads<RHO, NT>;
+  constexpr int WT = RHO / 32, GT = RHO / 4;  // words per tile row, row groups per tile column
+  const int C = (T + 3) >> 2, GR = GT + 2 * C;
+  const uint32_t magic = div_small_magic((uint32_t)GR);
+  ld.live = 0u;
+#pragma unroll
+  for (int k = 0; k < LD::UPT; ++k) {
+    const int u = (int)threadIdx.x + k * NT;
+    bool ok = false;
+    size_t off = 0;
+    if (u < LD::W * GR) {
+      int w, g;
+      bit_unit(u, GR, magic, w, g);
+      const int dbx = w == 0 ? -1 : (w == LD::W - 1 ? 1 : 0);
+      const int j = w == 0 ? WT - 1 : (w == LD::W - 1 ? 0 : w - 1);  // column in its tile
+      const int dby = g < C ? -1 : (g < C + GT ? 0 : 1);
+      const int yb = 4 * (g - C) - dby * RHO;  // first row in its tile: 0 .. rho - 4
+      const int32_t om = nbr[3 * (dby + 1) + dbx + 1];
+      ok = om >= 0;
+      off = (size_t)(uint32_t)om * bit_tile_words<RHO>() + (size_t)(j * RHO + yb);
+    }
+    ld.v[k] = ok ? *reinterpret_cast<const uint4 *>(in + off) : make_uint4(0u, 0u, 0u, 0u);
+    ld.live |= (ok ? 1u : 0u) << k;
+  }
+}
+
+// A pass's output as bit-packed tiles: the workgroup's own tile is
+// nbr[4]'s (read at the store, after the workgroup has synchronised).
+struct BitsOut {
+  uint32_t *out;
+  const int32_t *nbr;
+  static constexpr bool kBits = true;
+};
+
 // One tile pass: the rho x rho tile at block (bx, by) of the gasket of level
-// r advanced by T generations from mem.src to mem.dst, by NT threads, from
-// its region loads `ld` (issued by tb_load; a compact Mem is prepared).
-// `lds` holds tb_lds_bytes<RHO>(T) bytes (or more); the caller synchronises
-// the workgroup before reusing it.  stream_out: store the output
-// non-temporally (life_stream_stores).
-template <int RHO, int NT, class Mem>
+// r advanced by T generations, by NT threads, from its region loads `ld`
+// (RegionLoads issued by tb_load from the bytes, a compact Mem prepared; or
+// BitLoads issued by bits_load) to mem.dst (a byte Mem) or bit-packed tiles
+// (BitsOut).  `lds` holds tb_lds_bytes<RHO>(T) bytes (or more); the caller
+// synchronises the workgroup before reusing it.  stream_out: store the
+// output non-temporally (life_stream_stores).
+template <int RHO, int NT, class Mem, class Loads>
 __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint32_t by, int T,
-                                        uint32_t *lds, uint32_t *nseg_p,
-                                        const RegionLoads<RHO, NT> &ld, bool stream_out) {
+                                        uint32_t *lds, uint32_t *nseg_p, const Loads &ld,
+                                        bool stream_out) {
   uint32_t &nseg = *nseg_p;
   constexpr int kTbThreads = NT;
   // Region columns [X0-32, X0+RHO+32): the tile plus one 32-cell word each
@@ -384,9 +473,24 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   constexpr int NW = kTbThreads / 64;  // waves per workgroup
 
   // 1. bit-pack the region loads into plane 0 (each load unit's chunk goes
-  //    to its region row and chunk column).
-  uint16_t *p0h = reinterpret_cast<uint16_t *>(plane0);
-  {
+  //    to its region row and chunk column), or write the loaded words of
+  //    bit-packed tiles there (the rows of each unit inside the region).
+  if constexpr (Loads::kBits) {
+    const int C = (T + 3) >> 2, GR = RHO / 4 + 2 * C;
+    const uint32_t magic = div_small_magic((uint32_t)GR);
+#pragma unroll
+    for (int k = 0; k < Loads::UPT; ++k) {
+      if (!((ld.live >> k) & 1u)) continue;
+      int w, g;
+      bit_unit(tid + k * kTbThreads, GR, magic, w, g);
+      const int i = T - 4 * C + 4 * g;  // region row of the unit's first row
+      const uint32_t v[4] = {ld.v[k].x, ld.v[k].y, ld.v[k].z, ld.v[k].w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if ((unsigned)(i + q) < (unsigned)R) plane0[(i + q + 1) * PW + w + 1] = v[q];
+    }
+  } else {
+    uint16_t *p0h = reinterpret_cast<uint16_t *>(plane0);
     using LD = RegionLoads<RHO, NT>;
     constexpr int NC = RHO / 16;
 #pragma unroll
@@ -500,8 +604,19 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   //    granules without a gasket cell are never touched.  A compact tile, and
   //    the 32-byte rows of rho = 32, are rewritten whole: thread tid takes
   //    chunk column tid % TC of tile rows tid / TC, + RPS, ...
+  //    Bit-packed output: thread tid takes the 4-row runs tid, tid + NT, ...
+  //    of the tile's words, column by column.
   constexpr int TC = RHO / 16;  // 16-byte chunks per tile row
-  if constexpr (!Mem::kCompact && RHO >= 64) {
+  if constexpr (Mem::kBits) {
+    constexpr int GT = RHO / 4;  // 4-row runs per word column
+    const uint32_t *fw = (T & 1) ? plane1 : plane0;
+    uint32_t *o = mem.out + (size_t)(uint32_t)mem.nbr[4] * bit_tile_words<RHO>();
+    for (int u = tid; u < (RHO / 32) * GT; u += kTbThreads) {
+      const int j = u / GT, g = u % GT;
+      const uint32_t *f = fw + (T + 1 + 4 * g) * PW + 2 + j;
+      *reinterpret_cast<uint4 *>(o + j * RHO + 4 * g) = make_uint4(f[0], f[PW], f[2 * PW], f[3 * PW]);
+    }
+  } else if constexpr (!Mem::kCompact && RHO >= 64) {
     constexpr int NS = TileUnitTable<RHO>::units.nstore;
     for (int u = wave; u < NS; u += NW) {
       const uint32_t pr = kTileUnits<RHO>.store_pairs[u];
@@ -559,6 +674,48 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__
   RegionLoads<RHO, NT> ld;
   tb_load<RHO, NT>(mem, r, bx, by, T, ld);
   tb_tile<RHO, NT>(mem, r, bx, by, T, lds, &nseg, ld, stream_out != 0);
+}
+
+// A pass with bit-packed tiles on either side (SRC_BITS: the input, DST_BITS:
+// the output) and the byte embedding on the other, if any: the passes of a
+// multi-pass run after the first read bits, those before the last write
+// them.  The 3 x 3 blocks' omegas are found first, into LDS; with a byte
+// input its loads are issued before the workgroup waits for them.
+template <int RHO, bool LAMBDA, bool SRC_BITS, bool DST_BITS>
+__global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb_bits(
+    const void *__restrict__ in, void *__restrict__ out, int r, int rb, uint64_t tile_base,
+    uint64_t ntiles, int T, int stream_out) {
+  static_assert(SRC_BITS || DST_BITS, "byte-to-byte passes are k_life_tb");
+  constexpr int NT = tb_threads<RHO>();
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ uint32_t nseg;
+  __shared__ int32_t nbr[9];
+  const uint64_t t = tile_base + logical_group();
+  if (t >= ntiles) return;
+  uint32_t bx, by;
+  if (!tile_block<LAMBDA>(t, rb, bx, by)) return;
+  const int tid = (int)threadIdx.x;
+  auto run = [&](const auto &ld) {
+    if constexpr (DST_BITS) {
+      const BitsOut mem{static_cast<uint32_t *>(out), nbr};
+      tb_tile<RHO, NT>(mem, r, bx, by, T, lds, &nseg, ld, false);
+    } else {
+      const DenseMem mem{nullptr, static_cast<uint8_t *>(out), r};
+      tb_tile<RHO, NT>(mem, r, bx, by, T, lds, &nseg, ld, stream_out != 0);
+    }
+  };
+  if constexpr (SRC_BITS) {
+    neighbour_omegas(tid, bx, by, rb, nbr);
+    __syncthreads();
+    BitLoads<RHO, NT> ld;
+    bits_load<RHO, NT>(static_cast<const uint32_t *>(in), nbr, T, ld);
+    run(ld);
+  } else {
+    RegionLoads<RHO, NT> ld;
+    tb_load<RHO, NT>(DenseMem{static_cast<const uint8_t *>(in), nullptr, r}, r, bx, by, T, ld);
+    neighbour_omegas(tid, bx, by, rb, nbr);  // read at the store, after tb_tile's barriers
+    run(ld);
+  }
 }
 
 // One workgroup per tile of a gasket in block-compacted storage (lambda
@@ -654,6 +811,44 @@ hipError_t life_tb_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out
   return hipSuccess;
 }
 
+// Bytes of one bit-packed state of tiles of side RHO at block level rb.
+template <int RHO>
+size_t bit_state_bytes(int rb) {
+  uint64_t t = 1;
+  for (int i = 0; i < rb; ++i) t *= 3;
+  return (size_t)t * bit_tile_words<RHO>() * sizeof(uint32_t);
+}
+
+template <int RHO, bool LAMBDA>
+hipError_t life_tb_bits_map(const PassArgs &a, int T, const void *in, bool in_bits, void *out,
+                            bool out_bits) {
+  const size_t lds = tb_lds_bytes<RHO>(T);
+  // a byte output streams when it and the bits read exceed the cache; bits
+  // written are read by the next pass
+  const uint64_t touched = life_touched_bytes(a.r) / 2 + bit_state_bytes<RHO>(a.rb);
+  const int stream_out = !out_bits && life_stream_stores(touched) ? 1 : 0;
+  auto k = in_bits ? (out_bits ? k_life_tb_bits<RHO, LAMBDA, true, true>
+                               : k_life_tb_bits<RHO, LAMBDA, true, false>)
+                   : k_life_tb_bits<RHO, LAMBDA, false, true>;
+  if (!in_bits && !out_bits) return hipErrorInvalidValue;
+  const uint64_t per_launch = 1ull << 22;
+  for (uint64_t g0 = 0; g0 < a.ntiles; g0 += per_launch) {
+    const uint64_t g = a.ntiles - g0 < per_launch ? a.ntiles - g0 : per_launch;
+    hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(tb_threads<RHO>()), lds, a.stream, in, out,
+                       a.r, a.rb, g0, a.ntiles, T, stream_out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int RHO>
+hipError_t life_tb_bits_rho(const PassArgs &a, int T, const void *in, bool in_bits, void *out,
+                            bool out_bits) {
+  return a.lambda ? life_tb_bits_map<RHO, true>(a, T, in, in_bits, out, out_bits)
+                  : life_tb_bits_map<RHO, false>(a, T, in, in_bits, out, out_bits);
+}
+
 template <int RHO>
 hipError_t life_tb_compact_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out) {
   const size_t lds = tb_lds_bytes<RHO>(T);
@@ -714,6 +909,28 @@ hipError_t launch_life_tb_compact(const PassArgs &a, int T, const uint8_t *in, u
 
 bool life_tb_supported(int rho) { return rho == 64 || rho == 128 || rho == 256; }
 bool life_tb_dense_supported(int rho) { return rho == 32 || life_tb_supported(rho); }
+
+size_t life_tb_bit_state_bytes(const PassArgs &a) {
+  switch (a.rho) {
+    case 32: return bit_state_bytes<32>(a.rb);
+    case 64: return bit_state_bytes<64>(a.rb);
+    case 128: return bit_state_bytes<128>(a.rb);
+    case 256: return bit_state_bytes<256>(a.rb);
+    default: return 0;
+  }
+}
+
+hipError_t launch_life_tb_bits(const PassArgs &a, int T, const void *in, bool in_bits, void *out,
+                               bool out_bits) {
+  if (T < 1 || T > kMaxStepsPerPass || !(in_bits || out_bits)) return hipErrorInvalidValue;
+  switch (a.rho) {
+    case 32: return life_tb_bits_rho<32>(a, T, in, in_bits, out, out_bits);
+    case 64: return life_tb_bits_rho<64>(a, T, in, in_bits, out, out_bits);
+    case 128: return life_tb_bits_rho<128>(a, T, in, in_bits, out, out_bits);
+    case 256: return life_tb_bits_rho<256>(a, T, in, in_bits, out, out_bits);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_life_tb(const PassArgs &a, int T, const uint8_t *in, uint8_t *out) {
   if (T < 1 || T > kMaxStepsPerPass) return hipErrorInvalidValue;

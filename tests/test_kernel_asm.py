@@ -54,12 +54,30 @@ def _waited_at_once(lines):
     return bad
 
 
+def _bit_loads_per_thread(name):
+    """Region loads per thread of a pass that reads bit-packed tiles (None
+    for a pass reading bytes): 4-row units of the region's word columns
+    (the tile's, one each side) over its rows at 32 generations, spread over
+    the workgroup's threads."""
+    m = re.search(r"k_life_tb_bitsILi(\d+)ELb[01]ELb1ELb[01]E", name)
+    if not m:
+        return None
+    rho = int(m.group(1))
+    threads = 512 if rho >= 256 else 256
+    units = (rho // 32 + 2) * (rho // 4 + 2 * 8)
+    return -(-units // threads)
+
+
 def test_tile_pass_region_loads_stay_in_flight(asm):
     kernels = list(_kernels(asm))
-    assert len(kernels) >= 8  # dense (both maps, four sides), compact and batch variants
+    # dense (both maps, four sides), compact, batch, and the passes to and
+    # from bit-packed tiles (both maps, four sides, three directions)
+    assert len(kernels) >= 8 + 24
     for name, lines in kernels:
         loads = sum(1 for l in lines if re.match(r"(global|flat)_load_dwordx4\b", l))
-        assert loads >= 2, name  # a wave's batch of region loads (one per load unit)
+        per_thread = _bit_loads_per_thread(name)
+        # a wave's batch of region loads (one per load unit)
+        assert loads >= (2 if per_thread is None else per_thread), name
         assert _waited_at_once(lines) == 0, name
 
 
