@@ -19,8 +19,11 @@
 //     and used for three output rows; the 3 x 3 sum and the B3/S23 rule are
 //     evaluated on the bit planes, one v_bitop3 per three-input function,
 //     and masked to the gasket.
-//     Planes ping-pong with a barrier between generations.  Cells outside the
-//     region are taken as dead; the wrong values this makes at the region's
+//     One plane is updated in place: every segment computes its rows into
+//     registers, a barrier, then stores them, a barrier (one plane instead of
+//     two lets 8 workgroups share a compute unit at rho = 256, so nearly all
+//     32 of its wave slots run segments).  Cells outside the region are taken
+//     as dead; the wrong values this makes at the region's
 //     cut edges move inward one cell per generation and never reach the tile
 //     in T generations.
 //  4. Unpack the tile and store every 64-byte granule that holds a gasket
@@ -35,16 +38,19 @@ namespace {
 // Workgroup shape; the defaults are the measured best on MI355X and can be
 // overridden at build time.
 #ifndef SG_TB_THREADS
-#define SG_TB_THREADS 0  // 0: 512 threads for rho = 256, 256 otherwise
+#define SG_TB_THREADS 0  // 0: 256 threads
 #endif
 #ifndef SG_TB_SEG_ROWS
 #define SG_TB_SEG_ROWS 5
 #endif
 template <int RHO>
 constexpr int tb_threads() {
-  return SG_TB_THREADS > 0 ? SG_TB_THREADS : (RHO >= 256 ? 512 : 256);
+  return SG_TB_THREADS > 0 ? SG_TB_THREADS : 256;
 }
 constexpr int kSegRows = SG_TB_SEG_ROWS;      // rows per vertical segment of a generation
+// Waves per SIMD the dense, bit and compact tile passes are compiled for
+// (at most 64 VGPRs): 8 workgroups of 256 threads per compute unit.
+constexpr int kTbWavesPerSimd = 8;
 
 // Plane pitch (words per plane row) for a region W words wide.  Threads that
 // run consecutive segments of one word column touch rows kSegRows apart; a
@@ -449,14 +455,13 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   const int yr0 = Y0 - T;  // row of region row 0
 
   uint32_t *plane0 = lds;
-  uint32_t *plane1 = lds + PR * PW;
-  uint32_t *rowpat = plane1 + PR * PW;  // RP: gasket pattern of each region row
+  uint32_t *rowpat = plane0 + PR * PW;  // RP: gasket pattern of each region row
   uint32_t *segs = rowpat + RP;         // W * NB: listed segments
 
   {
-    // both planes cleared, 16 bytes per store (the region loads are in flight)
+    // the plane cleared, 16 bytes per store (the region loads are in flight)
     constexpr int kAlign = 4;
-    const int words = 2 * PR * PW, n4 = words / kAlign;
+    const int words = PR * PW, n4 = words / kAlign;
     uint4 *z = reinterpret_cast<uint4 *>(lds);
     for (int i = tid; i < n4; i += kTbThreads) z[i] = make_uint4(0u, 0u, 0u, 0u);
     for (int i = kAlign * n4 + tid; i < words; i += kTbThreads) lds[i] = 0u;
@@ -567,15 +572,14 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   }
   const int wave0 = __builtin_amdgcn_readfirstlane(tid) & ~63;  // the wave's first thread
   for (int s = 0; s < T; ++s) {
-    const uint32_t *src = (s & 1) ? plane1 : plane0;
-    uint32_t *dst = (s & 1) ? plane0 : plane1;
+    const uint32_t *src = plane0;
+    uint32_t outw[KSEG][L];  // the generation's new rows, stored once every read is done
 #pragma unroll
     for (int kk = 0; kk < KSEG; ++kk) {
       if (wave0 + kk * kTbThreads >= ns) break;  // this wave holds no segment here
       if (s >= slim[kk]) continue;               // cannot reach the tile any more
       const int idx0 = sidx[kk];
-      // all rows the segment reads, before any store (the planes may alias as
-      // far as the compiler knows, so loads are not moved past stores)
+      // all rows the segment reads, their loads issued together
       uint32_t row[L + 2][3];
 #pragma unroll
       for (int q = 0; q < L + 2; ++q) {
@@ -589,14 +593,22 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
 #pragma unroll
       for (int q = 0; q < L; ++q) {
         const RowSums dn = row_sums(row[q + 2][0], row[q + 2][1], row[q + 2][2]);
-        dst[idx0 + q * PW] = life_rule(up, mid, dn, smask[kk][q]);
+        outw[kk][q] = life_rule(up, mid, dn, smask[kk][q]);
         up = mid;
         mid = dn;
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KSEG; ++kk) {
+      if (wave0 + kk * kTbThreads >= ns) break;
+      if (s >= slim[kk]) continue;
+#pragma unroll
+      for (int q = 0; q < L; ++q) plane0[sidx[kk] + q * PW] = outw[kk][q];
+    }
+    __syncthreads();
   }
-  const uint16_t *fin = reinterpret_cast<const uint16_t *>((T & 1) ? plane1 : plane0);
+  const uint16_t *fin = reinterpret_cast<const uint16_t *>(plane0);
 
   // 4. unpack and store the tile.  In the embedding, a wave takes the store
   //    units w, w + NW, ... (TileUnits): 16 rows of one 64-byte granule that
@@ -609,7 +621,7 @@ __device__ __forceinline__ void tb_tile(const Mem &mem, int r, uint32_t bx, uint
   constexpr int TC = RHO / 16;  // 16-byte chunks per tile row
   if constexpr (Mem::kBits) {
     constexpr int GT = RHO / 4;  // 4-row runs per word column
-    const uint32_t *fw = (T & 1) ? plane1 : plane0;
+    const uint32_t *fw = plane0;
     uint32_t *o = mem.out + (size_t)(uint32_t)mem.nbr[4] * bit_tile_words<RHO>();
     for (int u = tid; u < (RHO / 32) * GT; u += kTbThreads) {
       const int j = u / GT, g = u % GT;
@@ -657,13 +669,12 @@ __device__ __forceinline__ bool tile_block(uint64_t t, int rb, uint32_t &bx, uin
 
 // One workgroup per tile of one gasket.  Its region loads are issued first,
 // so they are in flight while the LDS planes are cleared.
-template <int RHO, bool LAMBDA>
-__global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__restrict__ in,
+template <int RHO, bool LAMBDA, int NT>
+__global__ __launch_bounds__(NT, kTbWavesPerSimd) void k_life_tb(const uint8_t *__restrict__ in,
                                                                uint8_t *__restrict__ out, int r,
                                                                int rb, uint64_t tile_base,
                                                                uint64_t ntiles, int T,
                                                                int stream_out) {
-  constexpr int NT = tb_threads<RHO>();
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t nseg;
   const uint64_t t = tile_base + logical_group();
@@ -681,12 +692,11 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb(const uint8_t *__
 // multi-pass run after the first read bits, those before the last write
 // them.  The 3 x 3 blocks' omegas are found first, into LDS; with a byte
 // input its loads are issued before the workgroup waits for them.
-template <int RHO, bool LAMBDA, bool SRC_BITS, bool DST_BITS>
-__global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb_bits(
+template <int RHO, bool LAMBDA, bool SRC_BITS, bool DST_BITS, int NT>
+__global__ __launch_bounds__(NT, kTbWavesPerSimd) void k_life_tb_bits(
     const void *__restrict__ in, void *__restrict__ out, int r, int rb, uint64_t tile_base,
     uint64_t ntiles, int T, int stream_out) {
   static_assert(SRC_BITS || DST_BITS, "byte-to-byte passes are k_life_tb");
-  constexpr int NT = tb_threads<RHO>();
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ uint32_t nseg;
   __shared__ int32_t nbr[9];
@@ -721,7 +731,7 @@ __global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb_bits(
 // One workgroup per tile of a gasket in block-compacted storage (lambda
 // order): tile omega is the workgroup's omega.
 template <int RHO>
-__global__ __launch_bounds__(tb_threads<RHO>()) void k_life_tb_compact(
+__global__ __launch_bounds__(tb_threads<RHO>(), kTbWavesPerSimd) void k_life_tb_compact(
     const uint8_t *__restrict__ in, uint8_t *__restrict__ out, int r, int rb,
     uint64_t tile_base, uint64_t ntiles, int T, int stream_out) {
   extern __shared__ __align__(16) uint32_t lds[];
@@ -755,7 +765,7 @@ __device__ __forceinline__ void batch_tile(const DenseMem &mem, int r, uint32_t 
 // pass on that item's buffers, with that item's tile side (up to MAXRHO) and
 // generation count.
 template <int MAXRHO, int NT>
-__global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restrict__ items,
+__global__ __launch_bounds__(NT, kTbWavesPerSimd) void k_life_tb_batch(const BatchItem *__restrict__ items,
                                                       int count, uint64_t total_tiles,
                                                       int stream_out) {
   extern __shared__ __align__(16) uint32_t lds[];
@@ -785,30 +795,52 @@ __global__ __launch_bounds__(NT) void k_life_tb_batch(const BatchItem *__restric
 
 template <int RHO>
 size_t tb_lds_bytes(int T) {
-  // the layout of tb_tile: two planes, the row patterns, and a segment list
+  // the layout of tb_tile: the plane, the row patterns, and a segment list
   // of up to W * NB entries (W = the tile's words plus a halo word each side)
   const int W = RHO / 32 + 2, PW = plane_pitch(W), R = RHO + 2 * T;
   const int NB = (R + kSegRows - 1) / kSegRows, RP = NB * kSegRows, PR = RP + 2;
-  return sizeof(uint32_t) * (size_t)(2 * PR * PW + RP + W * NB);
+  return sizeof(uint32_t) * (size_t)(PR * PW + RP + W * NB);
 }
 
+// Threads per workgroup of a dense or bit pass.  tb_threads (256: 8
+// workgroups share a compute unit, so nearly every wave slot runs segments)
+// once the grid fills the chip; 512 at rho = 256 when every gasket tile runs
+// at once (at most 256 compute units x 4 workgroups of 512), where a tile's
+// latency is the pass's and twice the threads halve the segments per wave.
+constexpr uint64_t kWideTileLimit = 1024;
 template <int RHO>
-hipError_t life_tb_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out) {
+bool tb_wide(const PassArgs &a) {
+  if (RHO < 256 || tb_threads<RHO>() != 256) return false;
+  uint64_t tiles = 1;  // gasket tiles, for either map
+  for (int i = 0; i < a.rb && tiles <= kWideTileLimit; ++i) tiles *= 3;
+  return tiles <= kWideTileLimit;
+}
+
+template <int RHO, int NT>
+hipError_t life_tb_launch(const PassArgs &a, int T, const uint8_t *in, uint8_t *out) {
   const size_t lds = tb_lds_bytes<RHO>(T);
   const int stream_out = life_stream_stores(life_touched_bytes(a.r)) ? 1 : 0;
   const uint64_t per_launch = 1ull << 22;
   for (uint64_t g0 = 0; g0 < a.ntiles; g0 += per_launch) {
     const uint64_t g = a.ntiles - g0 < per_launch ? a.ntiles - g0 : per_launch;
     if (a.lambda)
-      hipLaunchKernelGGL((k_life_tb<RHO, true>), dim3((unsigned)g), dim3(tb_threads<RHO>()), lds,
+      hipLaunchKernelGGL((k_life_tb<RHO, true, NT>), dim3((unsigned)g), dim3(NT), lds,
                          a.stream, in, out, a.r, a.rb, g0, a.ntiles, T, stream_out);
     else
-      hipLaunchKernelGGL((k_life_tb<RHO, false>), dim3((unsigned)g), dim3(tb_threads<RHO>()), lds,
+      hipLaunchKernelGGL((k_life_tb<RHO, false, NT>), dim3((unsigned)g), dim3(NT), lds,
                          a.stream, in, out, a.r, a.rb, g0, a.ntiles, T, stream_out);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+template <int RHO>
+hipError_t life_tb_rho(const PassArgs &a, int T, const uint8_t *in, uint8_t *out) {
+  if constexpr (RHO >= 256) {
+    if (tb_wide<RHO>(a)) return life_tb_launch<RHO, 512>(a, T, in, out);
+  }
+  return life_tb_launch<RHO, tb_threads<RHO>()>(a, T, in, out);
 }
 
 // Bytes of one bit-packed state of tiles of side RHO at block level rb.
@@ -819,7 +851,7 @@ size_t bit_state_bytes(int rb) {
   return (size_t)t * bit_tile_words<RHO>() * sizeof(uint32_t);
 }
 
-template <int RHO, bool LAMBDA>
+template <int RHO, bool LAMBDA, int NT>
 hipError_t life_tb_bits_map(const PassArgs &a, int T, const void *in, bool in_bits, void *out,
                             bool out_bits) {
   const size_t lds = tb_lds_bytes<RHO>(T);
@@ -827,14 +859,14 @@ hipError_t life_tb_bits_map(const PassArgs &a, int T, const void *in, bool in_bi
   // written are read by the next pass
   const uint64_t touched = life_touched_bytes(a.r) / 2 + bit_state_bytes<RHO>(a.rb);
   const int stream_out = !out_bits && life_stream_stores(touched) ? 1 : 0;
-  auto k = in_bits ? (out_bits ? k_life_tb_bits<RHO, LAMBDA, true, true>
-                               : k_life_tb_bits<RHO, LAMBDA, true, false>)
-                   : k_life_tb_bits<RHO, LAMBDA, false, true>;
+  auto k = in_bits ? (out_bits ? k_life_tb_bits<RHO, LAMBDA, true, true, NT>
+                               : k_life_tb_bits<RHO, LAMBDA, true, false, NT>)
+                   : k_life_tb_bits<RHO, LAMBDA, false, true, NT>;
   if (!in_bits && !out_bits) return hipErrorInvalidValue;
   const uint64_t per_launch = 1ull << 22;
   for (uint64_t g0 = 0; g0 < a.ntiles; g0 += per_launch) {
     const uint64_t g = a.ntiles - g0 < per_launch ? a.ntiles - g0 : per_launch;
-    hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(tb_threads<RHO>()), lds, a.stream, in, out,
+    hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(NT), lds, a.stream, in, out,
                        a.r, a.rb, g0, a.ntiles, T, stream_out);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -845,8 +877,14 @@ hipError_t life_tb_bits_map(const PassArgs &a, int T, const void *in, bool in_bi
 template <int RHO>
 hipError_t life_tb_bits_rho(const PassArgs &a, int T, const void *in, bool in_bits, void *out,
                             bool out_bits) {
-  return a.lambda ? life_tb_bits_map<RHO, true>(a, T, in, in_bits, out, out_bits)
-                  : life_tb_bits_map<RHO, false>(a, T, in, in_bits, out, out_bits);
+  constexpr int NT = tb_threads<RHO>();
+  if constexpr (RHO >= 256) {
+    if (tb_wide<RHO>(a))
+      return a.lambda ? life_tb_bits_map<RHO, true, 512>(a, T, in, in_bits, out, out_bits)
+                      : life_tb_bits_map<RHO, false, 512>(a, T, in, in_bits, out, out_bits);
+  }
+  return a.lambda ? life_tb_bits_map<RHO, true, NT>(a, T, in, in_bits, out, out_bits)
+                  : life_tb_bits_map<RHO, false, NT>(a, T, in, in_bits, out, out_bits);
 }
 
 template <int RHO>
