@@ -240,6 +240,9 @@ SG_API int sg_compact_init_bernoulli(int r, int rho, uint64_t seed, uint64_t thr
  * 0 = 32) split as sg_ca_steps splits them;
  * every pass rewrites its output tiles whole, so d_out and d_work need no
  * zeroing.  All three: compact-sized, 16-byte aligned, non-overlapping.
+ * With two or more passes the state between them is kept in d_work as
+ * bit-packed tiles (one bit per cell, an eighth of the compact bytes);
+ * d_work's contents after the call are unspecified.
  * Errors: SG_EINVAL, SG_EALIAS, SG_EHIP. */
 SG_API int sg_ca_steps_compact(int r, int rho, int steps, int steps_per_pass,
                                const uint8_t *d_in, uint8_t *d_out, uint8_t *d_work,

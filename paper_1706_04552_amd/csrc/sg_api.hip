@@ -401,13 +401,18 @@ SG_API int sg_ca_steps_compact(int r, int rho, int steps, int steps_per_pass,
   SG_INJECT();
   if (steps == 0)
     return hip_status(hipMemcpyAsync(d_out, d_in, bytes, hipMemcpyDeviceToDevice, a.stream));
-  const uint8_t *src = d_in;
+  if (passes == 1) return hip_status(sg::launch_life_tb_compact(a, steps, d_in, d_out));
+  // between passes the state is bit-packed tiles, two of them in d_work
+  // (each an eighth of a compact state): bytes in, bits, ..., bits, bytes out
+  const size_t half = (sg::life_tb_bit_state_bytes(a) + 255) & ~(size_t)255;
+  void *bits[2] = {d_work, d_work + half};
   for (int k = 1; k <= passes; ++k) {
-    uint8_t *dst = ((passes - k) % 2 == 0) ? d_out : d_work;
     const int T = pass_steps(steps, passes, k);
-    const hipError_t e = sg::launch_life_tb_compact(a, T, src, dst);
+    const bool first = k == 1, last = k == passes;
+    const void *src = first ? static_cast<const void *>(d_in) : bits[k % 2];
+    void *dst = last ? static_cast<void *>(d_out) : bits[(k + 1) % 2];
+    const hipError_t e = sg::launch_life_tb_compact_bits(a, T, src, !first, dst, !last);
     if (e != hipSuccess) return hip_status(e);
-    src = dst;
   }
   return SG_OK;
 }

@@ -76,6 +76,10 @@ hipError_t launch_compact_copy(const PassArgs &a, bool pack, const uint8_t *src,
 hipError_t launch_compact_init(const PassArgs &a, uint64_t seed, uint64_t threshold,
                                uint8_t *dst);
 hipError_t launch_life_tb_compact(const PassArgs &a, int T, const uint8_t *in, uint8_t *out);
+// The compact pass with bit-packed tiles (as launch_life_tb_bits) as its
+// input and/or output, compact byte tiles on the other side.
+hipError_t launch_life_tb_compact_bits(const PassArgs &a, int T, const void *in, bool in_bits,
+                                       void *out, bool out_bits);
 
 // Temporally blocked FP32 diffusion: T steps per pass, T in
 // [1, kMaxDiffuseStepsPerPass], for tile sides rho in {16, 32, 64}.

@@ -749,6 +749,45 @@ __global__ __launch_bounds__(tb_threads<RHO>(), kTbWavesPerSimd) void k_life_tb_
   tb_tile<RHO, tb_threads<RHO>()>(mem, r, bx, by, T, lds, &nseg, ld, stream_out != 0);
 }
 
+// A pass over block-compacted storage with bit-packed tiles (the same
+// lambda order: tile omega is the workgroup's omega) as its input, its
+// output, or both, and compact byte tiles on the other side, if any.
+template <int RHO, bool SRC_BITS, bool DST_BITS>
+__global__ __launch_bounds__(tb_threads<RHO>(), kTbWavesPerSimd) void k_life_tb_compact_bits(
+    const void *__restrict__ in, void *__restrict__ out, int r, int rb, uint64_t tile_base,
+    uint64_t ntiles, int T, int stream_out) {
+  static_assert(SRC_BITS || DST_BITS, "byte-to-byte passes are k_life_tb_compact");
+  constexpr int NT = tb_threads<RHO>();
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ uint32_t nseg;
+  __shared__ int32_t nbr[9];
+  const uint64_t t = tile_base + logical_group();
+  if (t >= ntiles) return;
+  uint32_t bx, by;
+  lambda_decode((uint32_t)t, rb, bx, by);  // storage order
+  neighbour_omegas((int)threadIdx.x, bx, by, rb, nbr);
+  __syncthreads();  // the neighbour tiles' omegas, for either side
+  auto run = [&](const auto &ld) {
+    if constexpr (DST_BITS) {
+      const BitsOut mem{static_cast<uint32_t *>(out), nbr};
+      tb_tile<RHO, NT>(mem, r, bx, by, T, lds, &nseg, ld, false);
+    } else {
+      const CompactMem<RHO> mem{nullptr, static_cast<uint8_t *>(out), nbr, (int)bx, (int)by};
+      tb_tile<RHO, NT>(mem, r, bx, by, T, lds, &nseg, ld, stream_out != 0);
+    }
+  };
+  if constexpr (SRC_BITS) {
+    BitLoads<RHO, NT> ld;
+    bits_load<RHO, NT>(static_cast<const uint32_t *>(in), nbr, T, ld);
+    run(ld);
+  } else {
+    const CompactMem<RHO> src{static_cast<const uint8_t *>(in), nullptr, nbr, (int)bx, (int)by};
+    RegionLoads<RHO, NT> ld;
+    tb_load<RHO, NT>(src, r, bx, by, T, ld);
+    run(ld);
+  }
+}
+
 // One tile of a batched pass: its region loads, then the tile pass.
 template <int RHO, int NT>
 __device__ __forceinline__ void batch_tile(const DenseMem &mem, int r, uint32_t bx, uint32_t by,
@@ -903,6 +942,28 @@ hipError_t life_tb_compact_rho(const PassArgs &a, int T, const uint8_t *in, uint
   return hipSuccess;
 }
 
+template <int RHO>
+hipError_t life_tb_compact_bits_rho(const PassArgs &a, int T, const void *in, bool in_bits,
+                                    void *out, bool out_bits) {
+  const size_t lds = tb_lds_bytes<RHO>(T);
+  // a compact byte output streams when it and the bits read exceed the cache
+  const uint64_t touched = a.ntiles * RHO * RHO + bit_state_bytes<RHO>(a.rb);
+  const int stream_out = !out_bits && life_stream_stores(touched) ? 1 : 0;
+  if (!in_bits && !out_bits) return hipErrorInvalidValue;
+  auto k = in_bits ? (out_bits ? k_life_tb_compact_bits<RHO, true, true>
+                               : k_life_tb_compact_bits<RHO, true, false>)
+                   : k_life_tb_compact_bits<RHO, false, true>;
+  const uint64_t per_launch = 1ull << 22;
+  for (uint64_t g0 = 0; g0 < a.ntiles; g0 += per_launch) {
+    const uint64_t g = a.ntiles - g0 < per_launch ? a.ntiles - g0 : per_launch;
+    hipLaunchKernelGGL(k, dim3((unsigned)g), dim3(tb_threads<RHO>()), lds, a.stream, in, out,
+                       a.r, a.rb, g0, a.ntiles, T, stream_out);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template <int RHO, int NT>
 hipError_t life_tb_batch_rho(const BatchItem *d_items, int count, uint64_t total_tiles,
                              int max_steps, int groups, bool stream_out, hipStream_t stream) {
@@ -941,6 +1002,17 @@ hipError_t launch_life_tb_compact(const PassArgs &a, int T, const uint8_t *in, u
     case 64: return life_tb_compact_rho<64>(a, T, in, out);
     case 128: return life_tb_compact_rho<128>(a, T, in, out);
     case 256: return life_tb_compact_rho<256>(a, T, in, out);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_life_tb_compact_bits(const PassArgs &a, int T, const void *in, bool in_bits,
+                                       void *out, bool out_bits) {
+  if (T < 1 || T > kMaxStepsPerPass || !(in_bits || out_bits)) return hipErrorInvalidValue;
+  switch (a.rho) {
+    case 64: return life_tb_compact_bits_rho<64>(a, T, in, in_bits, out, out_bits);
+    case 128: return life_tb_compact_bits_rho<128>(a, T, in, in_bits, out, out_bits);
+    case 256: return life_tb_compact_bits_rho<256>(a, T, in, in_bits, out, out_bits);
     default: return hipErrorInvalidValue;
   }
 }

@@ -60,9 +60,13 @@ def _bit_loads_per_thread(name):
     (the tile's, one each side) over its rows at 32 generations, spread over
     the workgroup's threads."""
     m = re.search(r"k_life_tb_bitsILi(\d+)ELb[01]ELb1ELb[01]ELi(\d+)E", name)
-    if not m:
+    c = re.search(r"k_life_tb_compact_bitsILi(\d+)ELb1ELb[01]E", name)
+    if m:
+        rho, threads = int(m.group(1)), int(m.group(2))
+    elif c:
+        rho, threads = int(c.group(1)), 256
+    else:
         return None
-    rho, threads = int(m.group(1)), int(m.group(2))
     units = (rho // 32 + 2) * (rho // 4 + 2 * 8)
     return -(-units // threads)
 
@@ -71,8 +75,9 @@ def test_tile_pass_region_loads_stay_in_flight(asm):
     kernels = list(_kernels(asm))
     # dense (both maps, four sides; rho = 256 at two workgroup sizes),
     # compact, batch, and the passes to and from bit-packed tiles (both maps,
-    # four sides, three directions; rho = 256 at two workgroup sizes)
-    assert len(kernels) >= 10 + 30
+    # four sides, three directions; rho = 256 at two workgroup sizes; and
+    # the compact ones, three sides, three directions)
+    assert len(kernels) >= 10 + 30 + 9
     for name, lines in kernels:
         loads = sum(1 for l in lines if re.match(r"(global|flat)_load_dwordx4\b", l))
         per_thread = _bit_loads_per_thread(name)
