@@ -193,8 +193,8 @@ SG_API int sg_diffuse_step(int map, int r, int rho, const float *d_in,
  * blocking).  Every cell update is the same FP32 arithmetic as
  * sg_diffuse_step, so the result equals `steps` calls of it bit for bit.
  *   steps_per_pass: 1 (one launch per step, any rho), 2..16 (rho in {16, 32,
- *     64}), or 0 for the library's choice (16 at rho = 16, 8 at rho = 32 and
- *     64, else 1).
+ *     64}), or 0 for the library's choice (16 at rho = 16 and 64, 8 at
+ *     rho = 32, else 1).
  *   d_in: read only.  d_out: the state after `steps` steps.  d_work: a third
  *     n * n float buffer, used when more than one pass runs (may be NULL
  *     otherwise).  All: device, 16-byte aligned, pairwise non-overlapping,

@@ -8,7 +8,7 @@
 //     4-cell chunks (DtTable: the chunks that hold a gasket cell within H
 //     stencil steps of the tile, whatever block they lie in), keeps those
 //     whose block holds gasket cells and that lie within T steps, and loads
-//     them; while the loads are in flight the two LDS planes are cleared.
+//     them; while the loads are in flight the LDS planes are cleared.
 //     Then the loaded chunks go to the first plane, and the ones that can
 //     still reach the tile (distance < T) are listed (wavefront ballot +
 //     prefix count), each as one word: its region index, its distance, its
@@ -21,8 +21,12 @@
 //     diffuse_cell, the function the one-step kernels use, as
 //     fma(w, fma(-deg, u, (W + E) + (N + S)), u); off the gasket w = 0 keeps
 //     the value, which is 0 (the inner fma is finite there).  A chunk's own
-//     values stay in registers; the neighbours come from the other plane, and
-//     the planes ping-pong with a barrier between steps;
+//     values stay in registers.  At rho >= 32 the neighbours come from one
+//     plane updated in place: every held chunk reads its neighbours and
+//     computes, a barrier, it stores its new values, a barrier (one plane
+//     lets twice the workgroups share a compute unit at rho = 64).  At
+//     rho = 16, whose workgroups already fill a compute unit's wave slots,
+//     two planes ping-pong with one barrier per step;
 //  4. store the tile, every 64-byte granule that holds a gasket cell in full.
 //
 // The 4-neighbour stencil moves information one cell per step, so a cell at
@@ -37,6 +41,7 @@
 // cannot reach the tile in the steps left.  Rows 0 and R - 1 of the region
 // are T cells from the tile, so no updated chunk reads outside the plane.
 #include <atomic>
+
 #include <type_traits>
 
 #include "sg_device.h"
@@ -54,8 +59,10 @@ template <int RHO, int H>
 struct DtGeom {
   static constexpr int CW = RHO + 2 * H;  // region columns = plane pitch (floats)
   static constexpr int CC = CW / 4;       // region chunks per row
-  // plane stride (floats): the largest region's rows, so the second plane is
-  // a fixed offset from the first and every LDS access of a step is a base
+  // one plane updated in place (rho >= 32), or two that ping-pong (rho = 16)
+  static constexpr bool kInPlace = RHO >= 32;
+  // plane stride (floats): the largest region's rows, so a second plane is a
+  // fixed offset from the first and every LDS access of a step is a base
   // register plus an immediate
   static constexpr int PLANE = (RHO + 2 * H) * CW;
   static_assert(PLANE * 4 + (2 * CW + 4) * 4 < 65536, "LDS offsets fit their 16-bit field");
@@ -176,8 +183,9 @@ __constant__ DtTable kDtTable = DtTableOf<RHO, H>::table;
 template <int RHO, int H>
 size_t dt_lds_bytes(int T) {
   using G = DtGeom<RHO, H>;
-  return sizeof(float) * ((size_t)G::PLANE + (size_t)(RHO + 2 * T) * G::CW) +
-         sizeof(uint32_t) * DtTableOf<RHO, H>::n;
+  const size_t planes = G::kInPlace ? (size_t)(RHO + 2 * T) * G::CW
+                                    : (size_t)G::PLANE + (size_t)(RHO + 2 * T) * G::CW;
+  return sizeof(float) * planes + sizeof(uint32_t) * DtTableOf<RHO, H>::n;
 }
 
 // Lane i receives lane i - 1's (wave_shr:1) or lane i + 1's (wave_shl:1)
@@ -234,7 +242,7 @@ __global__ __launch_bounds__((DtGeom<RHO, H>::NT)) void k_diffuse_tb(const float
   const int nslots = R * G::CC;
   // region cell (i, x) of a plane is at i * CW + x
   float *plane0 = flds;
-  float *plane1 = flds + G::PLANE;
+  float *plane1 = G::kInPlace ? plane0 : flds + G::PLANE;  // the ping-pong partner
   uint32_t *list = reinterpret_cast<uint32_t *>(plane1 + R * G::CW);
 
   // the 3 x 3 blocks around the tile that hold gasket cells: bit b =
@@ -261,7 +269,8 @@ __global__ __launch_bounds__((DtGeom<RHO, H>::NT)) void k_diffuse_tb(const float
   }
   {
     float4 *z = reinterpret_cast<float4 *>(flds);
-    for (int e = tid; e < G::PLANE / 4 + nslots; e += NT) z[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const int n4 = G::kInPlace ? nslots : G::PLANE / 4 + nslots;
+    for (int e = tid; e < n4; e += NT) z[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   }
   if (tid == 0) nchunk = 0u;
   __syncthreads();
@@ -342,8 +351,8 @@ __global__ __launch_bounds__((DtGeom<RHO, H>::NT)) void k_diffuse_tb(const float
     cur[kk] = kk < kheld && steps_live[kk] > 0 ? *reinterpret_cast<const float4 *>(plane0 + off[kk])
                                  : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   // One step from the plane at float offset SRC to the one at DST (0 or
-  // PLANE): every access is relative to the chunk's north neighbour in
-  // plane 0, so its address is one register plus an immediate.
+  // PLANE; both 0 in place): every access is relative to the chunk's north
+  // neighbour in plane 0, so its address is one register plus an immediate.
   auto step = [&](int s, auto src_off, auto dst_off) {
     constexpr int SRC = decltype(src_off)::value, DST = decltype(dst_off)::value;
 #pragma unroll
@@ -369,18 +378,31 @@ __global__ __launch_bounds__((DtGeom<RHO, H>::NT)) void k_diffuse_tb(const float
                               __builtin_fmaf(-deg[kk][j], cu[j], (w + ee) + (nu[j] + su[j])), cu[j]);
       }
       cur[kk] = make_float4(o[0], o[1], o[2], o[3]);
-      *reinterpret_cast<float4 *>(q + DST + G::CW) = cur[kk];
+      if constexpr (!G::kInPlace) *reinterpret_cast<float4 *>(q + DST + G::CW) = cur[kk];
     }
-    __syncthreads();
+    __syncthreads();  // in place: every read of the step is done
+    if constexpr (G::kInPlace) {
+#pragma unroll
+      for (int kk = 0; kk < KE; ++kk) {
+        if (kk >= kheld) break;
+        if (s >= steps_live[kk]) continue;
+        *reinterpret_cast<float4 *>(plane0 + off[kk]) = cur[kk];
+      }
+      __syncthreads();
+    }
   };
   using Zero = std::integral_constant<int, 0>;
   using Second = std::integral_constant<int, G::PLANE>;
-  int s = 0;
-  for (; s + 1 < T; s += 2) {
-    step(s, Zero{}, Second{});
-    step(s + 1, Second{}, Zero{});
+  if constexpr (G::kInPlace) {
+    for (int s = 0; s < T; ++s) step(s, Zero{}, Zero{});
+  } else {
+    int s = 0;
+    for (; s + 1 < T; s += 2) {
+      step(s, Zero{}, Second{});
+      step(s + 1, Second{}, Zero{});
+    }
+    if (s < T) step(s, Zero{}, Second{});
   }
-  if (s < T) step(s, Zero{}, Second{});
   const float *fin = (T & 1) ? plane1 : plane0;
 
   // 4. store the tile, whole 64-byte granules (16 floats)
@@ -446,7 +468,7 @@ hipError_t diffuse_tb_rho(const PassArgs &a, int T, const float *in, float *out,
 }  // namespace
 
 bool diffuse_tb_supported(int rho) { return rho == 16 || rho == 32 || rho == 64; }
-int diffuse_tb_default_steps(int rho) { return rho == 16 ? 16 : 8; }
+int diffuse_tb_default_steps(int rho) { return rho == 32 ? 8 : 16; }
 
 hipError_t launch_diffuse_tb(const PassArgs &a, int T, const float *in, float *out,
                              float alpha) {

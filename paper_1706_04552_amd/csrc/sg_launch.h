@@ -86,8 +86,8 @@ hipError_t launch_life_tb_compact_bits(const PassArgs &a, int T, const void *in,
 constexpr int kMaxDiffuseStepsPerPass = 16;
 bool diffuse_tb_supported(int rho);
 // What steps_per_pass = 0 selects: the measured best pass length at this
-// tile side (16 at rho = 16, whose halo is cheap next to its setup; 8 at 32
-// and 64, where the wider region of a longer pass costs occupancy).
+// tile side (16 at rho = 16 and 64; 8 at 32, where a longer pass's wider
+// region costs more than its fewer passes save).
 int diffuse_tb_default_steps(int rho);
 hipError_t launch_diffuse_tb(const PassArgs &a, int T, const float *in, float *out,
                              float alpha);
