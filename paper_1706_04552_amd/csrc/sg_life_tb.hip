@@ -23,11 +23,17 @@
 //     registers, a barrier, then stores them, a barrier (one plane instead of
 //     two lets 8 workgroups share a compute unit at rho = 256, so nearly all
 //     32 of its wave slots run segments).  Cells outside the region are taken
-//     as dead; the wrong values this makes at the region's
-//     cut edges move inward one cell per generation and never reach the tile
-//     in T generations.
+//     as dead; the wrong values this makes at the region's cut edges move
+//     inward one cell per generation and never reach the tile in T
+//     generations.
 //  4. Unpack the tile and store every 64-byte granule that holds a gasket
 //     cell in full.
+//
+// Between the passes of a multi-pass run the state is bit-packed tiles
+// (bit_tile_words): the passes after the first read those words straight
+// into the plane instead of step 1's bytes, and the passes before the last
+// store the plane's tile words instead of step 4's bytes (k_life_tb_bits,
+// k_life_tb_compact_bits).
 #include "sg_device.h"
 #include "sg_launch.h"
 
@@ -668,7 +674,7 @@ __device__ __forceinline__ bool tile_block(uint64_t t, int rb, uint32_t &bx, uin
 }
 
 // One workgroup per tile of one gasket.  Its region loads are issued first,
-// so they are in flight while the LDS planes are cleared.
+// so they are in flight while the LDS plane is cleared.
 template <int RHO, bool LAMBDA, int NT>
 __global__ __launch_bounds__(NT, kTbWavesPerSimd) void k_life_tb(const uint8_t *__restrict__ in,
                                                                uint8_t *__restrict__ out, int r,
@@ -828,7 +834,7 @@ __global__ __launch_bounds__(NT, kTbWavesPerSimd) void k_life_tb_batch(const Bat
       batch_tile<(MAXRHO >= 256 ? 256 : 64), NT>(mem, it.r, bx, by, it.steps, lds, &nseg,
                                                  stream_out != 0);
     }
-    __syncthreads();  // the next tile reuses the LDS planes
+    __syncthreads();  // the next tile reuses the LDS plane
   }
 }
 
